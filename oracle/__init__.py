@@ -1,0 +1,213 @@
+"""CPU oracle for the matrix permanent -- test infrastructure only.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never loads it and
+shares no code with it; the two meet only through the seeded inputs that
+``paper_1904_06229_amd.inputs`` generates.
+
+The arithmetic lives in ``perm_oracle.c`` (plain C, long double / exact
+128-bit integers); this module only compiles it with gcc and marshals numpy
+arrays through ctypes.  Routes (see the C file for the passages they follow):
+
+* ``brute``         -- the n!-term definition (Sec. I, Eq. per), n <= 12.
+* ``ryser``         -- Ryser's 2^n-subset formula (Sec. II.A, Eq. ryser) in
+                       Gray order with a long-double Kahan sum (App. A).
+* ``ryser_range``   -- the raw signed Ryser sum over a subset-index range.
+* ``chunk_partial`` -- App. A ``subpermanent`` partial sum over a Gray-index
+                       range, each term formed directly (no walk).
+
+Real results come back as :class:`Pair` (an unevaluated double pair hi + lo
+holding the long-double value), complex ones as :class:`CPair`, integer ones
+as Python ``int``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+from fractions import Fraction
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "perm_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no fast-math: Kahan summation must survive)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-fPIC", "-shared", "-pthread", "-std=gnu11",
+             "-fno-fast-math", "-ffp-contract=off", _SRC, "-o", tmp])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB_PATH)
+    dp = ctypes.POINTER(ctypes.c_double)
+    up = ctypes.POINTER(ctypes.c_uint64)
+    bp = ctypes.POINTER(ctypes.c_uint8)
+    i, u64 = ctypes.c_int, ctypes.c_uint64
+    sig = {
+        "oracle_brute_real": ([dp, i, i, dp]),
+        "oracle_brute_complex": ([dp, i, i, dp]),
+        "oracle_brute_int": ([bp, i, i, up]),
+        "oracle_ryser_real": ([dp, i, i, i, dp]),
+        "oracle_ryser_complex": ([dp, i, i, i, dp]),
+        "oracle_ryser_int": ([bp, i, i, i, up]),
+        "oracle_ryser_real_range": ([dp, i, i, u64, u64, i, dp]),
+        "oracle_ryser_complex_range": ([dp, i, i, u64, u64, i, dp]),
+        "oracle_ryser_int_range": ([bp, i, i, u64, u64, i, up]),
+        "oracle_chunk_real": ([dp, i, i, u64, u64, i, dp]),
+        "oracle_chunk_complex": ([dp, i, i, u64, u64, i, dp]),
+        "oracle_chunk_int": ([bp, i, i, u64, u64, i, up]),
+        "oracle_default_threads": ([]),
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+@dataclass(frozen=True)
+class Pair:
+    """Real value hi + lo (both doubles)."""
+
+    hi: float
+    lo: float = 0.0
+
+    @property
+    def exact(self) -> Fraction:
+        return Fraction(self.hi) + Fraction(self.lo)
+
+    def __float__(self) -> float:
+        return float(self.hi)
+
+    def __neg__(self) -> "Pair":
+        return Pair(-self.hi, -self.lo)
+
+
+@dataclass(frozen=True)
+class CPair:
+    """Complex value (re.hi + re.lo) + i (im.hi + im.lo)."""
+
+    re: Pair
+    im: Pair
+
+    def __complex__(self) -> complex:
+        return complex(self.re.hi, self.im.hi)
+
+    def __neg__(self) -> "CPair":
+        return CPair(-self.re, -self.im)
+
+
+def _words_to_int(w) -> int:
+    """(low, high) 64-bit words of a value mod 2^128 -> signed Python int."""
+    v = int(w[0]) | (int(w[1]) << 64)
+    return v - (1 << 128) if v >= (1 << 127) else v
+
+
+def _prep(A):
+    A = np.asarray(A)
+    if A.ndim != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("square matrix expected")
+    n = A.shape[0]
+    if np.iscomplexobj(A):
+        M = np.asfortranarray(A, dtype=np.complex128)
+        kind = "complex"
+    elif A.dtype == np.uint8 or A.dtype == np.bool_:
+        M = np.asfortranarray(A, dtype=np.uint8)
+        kind = "int"
+    else:
+        M = np.asfortranarray(A, dtype=np.float64)
+        kind = "real"
+    return M, n, kind
+
+
+def _ptr(M, kind):
+    if kind == "int":
+        return M.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    return M.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _result(kind, buf):
+    if kind == "real":
+        return Pair(buf[0], buf[1])
+    if kind == "complex":
+        return CPair(Pair(buf[0], buf[1]), Pair(buf[2], buf[3]))
+    return _words_to_int(buf)
+
+
+def _outbuf(kind):
+    if kind == "int":
+        return (ctypes.c_uint64 * 2)()
+    return (ctypes.c_double * 4)()
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError(f"oracle {what}: invalid arguments")
+
+
+def brute(A):
+    """per(A) by the definition, all n! permutations (n <= 12)."""
+    lib = _load()
+    M, n, kind = _prep(A)
+    out = _outbuf(kind)
+    f = {"real": lib.oracle_brute_real, "complex": lib.oracle_brute_complex,
+         "int": lib.oracle_brute_int}[kind]
+    _check(f(_ptr(M, kind), n, max(n, 1), out), "brute")
+    return _result(kind, out)
+
+
+def ryser(A, threads: int = 0):
+    """per(A) by Ryser's formula over all 2^n subsets (n <= 40)."""
+    lib = _load()
+    M, n, kind = _prep(A)
+    out = _outbuf(kind)
+    f = {"real": lib.oracle_ryser_real, "complex": lib.oracle_ryser_complex,
+         "int": lib.oracle_ryser_int}[kind]
+    _check(f(_ptr(M, kind), n, max(n, 1), threads, out), "ryser")
+    return _result(kind, out)
+
+
+def ryser_range(A, k0: int, count: int, threads: int = 0):
+    """Raw sum over subset indices [k0, k0+count) of (-1)^|J| prod_i sum_{j in J} a_ij."""
+    lib = _load()
+    M, n, kind = _prep(A)
+    out = _outbuf(kind)
+    f = {"real": lib.oracle_ryser_real_range, "complex": lib.oracle_ryser_complex_range,
+         "int": lib.oracle_ryser_int_range}[kind]
+    _check(f(_ptr(M, kind), n, n, k0, count, threads, out), "ryser_range")
+    return _result(kind, out)
+
+
+def chunk_partial(A, g0: int, count: int, threads: int = 0):
+    """App. A partial sum over Gray indices [g0, g0+count): sum (-1)^(g+1) prod_i w_i.
+
+    For 0/1 (uint8) input the integer form with r = 2w is returned instead,
+    i.e. 2^n times the App. A partial sum, exactly (mod 2^128).
+    """
+    lib = _load()
+    M, n, kind = _prep(A)
+    out = _outbuf(kind)
+    f = {"real": lib.oracle_chunk_real, "complex": lib.oracle_chunk_complex,
+         "int": lib.oracle_chunk_int}[kind]
+    _check(f(_ptr(M, kind), n, n, g0, count, threads, out), "chunk_partial")
+    return _result(kind, out)
+
+
+def default_threads() -> int:
+    return _load().oracle_default_threads()

@@ -1,0 +1,656 @@
+/*
+ * CPU oracle for the matrix permanent -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test-suite, the smoke entry point and the CPU-baseline leg of the
+ * benchmark may load this library.  It shares no code, header, table or
+ * helper with the GPU library, and it includes nothing from it.
+ *
+ * Storage: column-major with leading dimension ld, a(i,j) = A[i + j*ld]
+ * (0-based i, j).  Complex matrices are interleaved (re, im) pairs, so
+ * a(i,j) = A[2*(i+j*ld)] + i*A[2*(i+j*ld)+1].  0/1 matrices are bytes.
+ *
+ * Four routes, each written from the paper (Lundow & Markstrom,
+ * "Efficient computation of permanents, with applications to Boson sampling
+ * and random matrices"):
+ *
+ *   O1 oracle_brute_*      The definition: sum over all n! permutations of
+ *                          the product of one entry per row (Sec. I, Eq. per).
+ *   O2 oracle_ryser_*      Ryser's inclusion-exclusion over all 2^n column
+ *                          subsets J (Sec. II.A, Eq. ryser), the subsets
+ *                          visited in Gray-code order (Sec. II.A), the terms
+ *                          added with Kahan summation (App. A, Kahan) in
+ *                          long double, partial sums of the threads stored in
+ *                          an array and added afterwards in a fixed order
+ *                          (Sec. II.B).
+ *   O3 oracle_ryser_i128   O2 on integer matrices with exact arithmetic
+ *                          modulo 2^128 (exact whenever |per| < 2^127).
+ *   O4 oracle_chunk_*      The half-range partial sum of App. A
+ *                          (subpermanent) over an explicit Gray-index range,
+ *                          every term's row-sum vector formed directly from
+ *                          the Gray code (App. A, Gray unranking), with no
+ *                          walk, so there is no drift.  Sign convention as in
+ *                          App. A: term g carries (-1)^(g+1), and
+ *                          per(A) = 2 (-1)^n * (sum over all 2^(n-1) terms).
+ *
+ * Threads (pthreads) only split index ranges evenly (App. A, distribute);
+ * every thread's partial result lands in an array that is added in index
+ * order, so the result does not depend on scheduling.
+ */
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <unistd.h>
+
+typedef unsigned __int128 u128;
+
+#define ORACLE_MAX_N 64
+#define ORACLE_MAX_THREADS 256
+
+/* ------------------------------------------------------------------------ */
+/* Small utilities                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* Kahan summation in long double (App. A, Kahan). */
+typedef struct {
+  long double s, b;
+} kahan_ld;
+
+static void kahan_add(kahan_ld* k, long double a) {
+  long double c = a - k->b;
+  long double t = k->s + c;
+  k->b = (t - k->s) - c;
+  k->s = t;
+}
+
+/* Split a long double into an unevaluated pair of doubles hi + lo. */
+static void ld_to_pair(long double x, double* out) {
+  double hi = (double)x;
+  out[0] = hi;
+  out[1] = (double)(x - (long double)hi);
+}
+
+static void u128_to_pair(u128 x, uint64_t* out) {
+  out[0] = (uint64_t)x;
+  out[1] = (uint64_t)(x >> 64);
+}
+
+/* App. A, distribute: cut a sequence of length total into m near-equal
+ * consecutive parts; part i starts at k and has length len. */
+static void distribute(uint64_t total, uint64_t m, uint64_t i, uint64_t* k,
+                       uint64_t* len) {
+  uint64_t q = total / m;
+  uint64_t r = total % m;
+  *k = i * q + (i < r ? i : r);
+  *len = q + (i < r ? 1 : 0);
+}
+
+static int pick_threads(int requested, uint64_t work_items) {
+  int t = requested;
+  if (t <= 0) {
+    long c = sysconf(_SC_NPROCESSORS_ONLN);
+    t = c > 0 ? (int)c : 1;
+  }
+  if (t > ORACLE_MAX_THREADS) t = ORACLE_MAX_THREADS;
+  if ((uint64_t)t > work_items) t = work_items > 0 ? (int)work_items : 1;
+  return t;
+}
+
+/* Gray code of k (App. A, Gray unranking). */
+static uint64_t gray(uint64_t k) { return k ^ (k >> 1); }
+
+static int popcount64(uint64_t x) { return __builtin_popcountll(x); }
+
+/* ------------------------------------------------------------------------ */
+/* O1: the definition, all n! permutations (Sec. I, Eq. per)                 */
+/* ------------------------------------------------------------------------ */
+
+/* Visit every permutation of {0..n-1} once (Heap's method). */
+typedef void (*perm_visitor)(const int* p, int n, void* ctx);
+
+static void for_each_permutation(int n, perm_visitor visit, void* ctx) {
+  int p[ORACLE_MAX_N], c[ORACLE_MAX_N];
+  for (int i = 0; i < n; ++i) {
+    p[i] = i;
+    c[i] = 0;
+  }
+  visit(p, n, ctx);
+  int i = 1;
+  while (i < n) {
+    if (c[i] < i) {
+      int a = (i % 2 == 0) ? 0 : c[i];
+      int t = p[a];
+      p[a] = p[i];
+      p[i] = t;
+      visit(p, n, ctx);
+      c[i] += 1;
+      i = 1;
+    } else {
+      c[i] = 0;
+      i += 1;
+    }
+  }
+}
+
+typedef struct {
+  const double* A;
+  int ld;
+  kahan_ld re, im;
+  u128 acc;
+  const uint8_t* B;
+} brute_ctx;
+
+static void visit_real(const int* p, int n, void* vctx) {
+  brute_ctx* x = (brute_ctx*)vctx;
+  long double prod = 1.0L;
+  for (int i = 0; i < n; ++i) prod *= (long double)x->A[i + (size_t)p[i] * x->ld];
+  kahan_add(&x->re, prod);
+}
+
+static void visit_complex(const int* p, int n, void* vctx) {
+  brute_ctx* x = (brute_ctx*)vctx;
+  long double pr = 1.0L, pi = 0.0L;
+  for (int i = 0; i < n; ++i) {
+    size_t o = 2 * (i + (size_t)p[i] * x->ld);
+    long double ar = x->A[o], ai = x->A[o + 1];
+    long double nr = pr * ar - pi * ai;
+    long double ni = pr * ai + pi * ar;
+    pr = nr;
+    pi = ni;
+  }
+  kahan_add(&x->re, pr);
+  kahan_add(&x->im, pi);
+}
+
+static void visit_int(const int* p, int n, void* vctx) {
+  brute_ctx* x = (brute_ctx*)vctx;
+  u128 prod = 1;
+  for (int i = 0; i < n; ++i) prod *= (u128)x->B[i + (size_t)p[i] * x->ld];
+  x->acc += prod;
+}
+
+/* out[0..1]: per(A) as hi + lo.  Returns 0, or -1 on bad arguments. */
+int oracle_brute_real(const double* A, int n, int ld, double* out) {
+  if (n < 0 || n > 12 || ld < n) return -1;
+  brute_ctx x;
+  memset(&x, 0, sizeof x);
+  x.A = A;
+  x.ld = ld;
+  for_each_permutation(n, visit_real, &x);
+  ld_to_pair(x.re.s, out);
+  return 0;
+}
+
+/* out[0..3]: re hi, re lo, im hi, im lo. */
+int oracle_brute_complex(const double* A, int n, int ld, double* out) {
+  if (n < 0 || n > 12 || ld < n) return -1;
+  brute_ctx x;
+  memset(&x, 0, sizeof x);
+  x.A = A;
+  x.ld = ld;
+  for_each_permutation(n, visit_complex, &x);
+  ld_to_pair(x.re.s, out);
+  ld_to_pair(x.im.s, out + 2);
+  return 0;
+}
+
+/* Unsigned byte entries; out[0..1]: per(A) mod 2^128 as (low, high) words. */
+int oracle_brute_int(const uint8_t* B, int n, int ld, uint64_t* out) {
+  if (n < 0 || n > 12 || ld < n) return -1;
+  brute_ctx x;
+  memset(&x, 0, sizeof x);
+  x.B = B;
+  x.ld = ld;
+  for_each_permutation(n, visit_int, &x);
+  u128_to_pair(x.acc, out);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O2 / O3: Ryser over all 2^n subsets in Gray order (Sec. II.A, Eq. ryser)  */
+/* ------------------------------------------------------------------------ */
+
+/* Row sums are formed from scratch at the first subset of a thread's range
+ * and again every RYSER_REFORM subsets, so long-double round-off in the
+ * running sums cannot build up along the walk. */
+#define RYSER_REFORM 1024u
+
+typedef struct {
+  const double* A;
+  const uint8_t* B;
+  int n, ld, is_complex;
+  uint64_t k0, len;
+  long double re, im; /* partial sums (already Kahan-compensated) */
+  u128 acc;
+} ryser_job;
+
+/* Sum over subsets J = gray(k), k in [k0, k0+len), of (-1)^|J| prod_i sum_{j in J} a_ij. */
+static void* ryser_real_worker(void* arg) {
+  ryser_job* jb = (ryser_job*)arg;
+  const int n = jb->n, ld = jb->ld;
+  long double r[ORACLE_MAX_N];
+  kahan_ld S = {0.0L, 0.0L};
+  for (uint64_t k = jb->k0; k < jb->k0 + jb->len; ++k) {
+    uint64_t J = gray(k);
+    if (k == jb->k0 || ((k - jb->k0) % RYSER_REFORM) == 0) {
+      for (int i = 0; i < n; ++i) {
+        r[i] = 0.0L;
+        for (int j = 0; j < n; ++j)
+          if ((J >> j) & 1) r[i] += (long double)jb->A[i + (size_t)j * ld];
+      }
+    } else {
+      /* gray(k) and gray(k-1) differ in exactly bit ctz(k). */
+      int j = __builtin_ctzll(k);
+      int added = (int)((J >> j) & 1);
+      for (int i = 0; i < n; ++i) {
+        long double a = (long double)jb->A[i + (size_t)j * ld];
+        r[i] = added ? r[i] + a : r[i] - a;
+      }
+    }
+    long double p = 1.0L;
+    for (int i = 0; i < n; ++i) p *= r[i];
+    kahan_add(&S, (popcount64(J) & 1) ? -p : p);
+  }
+  jb->re = S.s;
+  return NULL;
+}
+
+static void* ryser_complex_worker(void* arg) {
+  ryser_job* jb = (ryser_job*)arg;
+  const int n = jb->n, ld = jb->ld;
+  long double rr[ORACLE_MAX_N], ri[ORACLE_MAX_N];
+  kahan_ld Sr = {0.0L, 0.0L}, Si = {0.0L, 0.0L};
+  for (uint64_t k = jb->k0; k < jb->k0 + jb->len; ++k) {
+    uint64_t J = gray(k);
+    if (k == jb->k0 || ((k - jb->k0) % RYSER_REFORM) == 0) {
+      for (int i = 0; i < n; ++i) {
+        rr[i] = 0.0L;
+        ri[i] = 0.0L;
+        for (int j = 0; j < n; ++j)
+          if ((J >> j) & 1) {
+            size_t o = 2 * (i + (size_t)j * ld);
+            rr[i] += (long double)jb->A[o];
+            ri[i] += (long double)jb->A[o + 1];
+          }
+      }
+    } else {
+      int j = __builtin_ctzll(k);
+      int added = (int)((J >> j) & 1);
+      for (int i = 0; i < n; ++i) {
+        size_t o = 2 * (i + (size_t)j * ld);
+        long double ar = jb->A[o], ai = jb->A[o + 1];
+        rr[i] = added ? rr[i] + ar : rr[i] - ar;
+        ri[i] = added ? ri[i] + ai : ri[i] - ai;
+      }
+    }
+    long double pr = 1.0L, pi = 0.0L;
+    for (int i = 0; i < n; ++i) {
+      long double nr = pr * rr[i] - pi * ri[i];
+      long double ni = pr * ri[i] + pi * rr[i];
+      pr = nr;
+      pi = ni;
+    }
+    if (popcount64(J) & 1) {
+      pr = -pr;
+      pi = -pi;
+    }
+    kahan_add(&Sr, pr);
+    kahan_add(&Si, pi);
+  }
+  jb->re = Sr.s;
+  jb->im = Si.s;
+  return NULL;
+}
+
+/* Integer entries, arithmetic modulo 2^128 (unsigned wrap-around). */
+static void* ryser_int_worker(void* arg) {
+  ryser_job* jb = (ryser_job*)arg;
+  const int n = jb->n, ld = jb->ld;
+  int64_t r[ORACLE_MAX_N];
+  u128 S = 0;
+  for (uint64_t k = jb->k0; k < jb->k0 + jb->len; ++k) {
+    uint64_t J = gray(k);
+    if (k == jb->k0) {
+      for (int i = 0; i < n; ++i) {
+        r[i] = 0;
+        for (int j = 0; j < n; ++j)
+          if ((J >> j) & 1) r[i] += jb->B[i + (size_t)j * ld];
+      }
+    } else {
+      int j = __builtin_ctzll(k);
+      int added = (int)((J >> j) & 1);
+      for (int i = 0; i < n; ++i) {
+        int64_t a = jb->B[i + (size_t)j * ld];
+        r[i] = added ? r[i] + a : r[i] - a;
+      }
+    }
+    u128 p = 1;
+    for (int i = 0; i < n; ++i) p *= (u128)(__int128)r[i];
+    if (popcount64(J) & 1)
+      S -= p;
+    else
+      S += p;
+  }
+  jb->acc = S;
+  return NULL;
+}
+
+static int run_ryser(ryser_job* proto, uint64_t k0, uint64_t count, int nthreads,
+                     void* (*worker)(void*), ryser_job* jobs_out, int* used) {
+  int T = pick_threads(nthreads, count);
+  pthread_t th[ORACLE_MAX_THREADS];
+  for (int t = 0; t < T; ++t) {
+    jobs_out[t] = *proto;
+    uint64_t off, len;
+    distribute(count, (uint64_t)T, (uint64_t)t, &off, &len);
+    jobs_out[t].k0 = k0 + off;
+    jobs_out[t].len = len;
+  }
+  int started = 0;
+  for (int t = 0; t < T; ++t) {
+    if (pthread_create(&th[t], NULL, worker, &jobs_out[t]) != 0) break;
+    ++started;
+  }
+  for (int t = started; t < T; ++t) worker(&jobs_out[t]);
+  for (int t = 0; t < started; ++t) pthread_join(th[t], NULL);
+  *used = T;
+  return 0;
+}
+
+/*
+ * Partial Ryser sum over subset indices k in [k0, k0+count): the subset is
+ * J = gray(k), the term is (-1)^|J| prod_i sum_{j in J} a_ij.  The full
+ * permanent is (-1)^n times the sum over k in [0, 2^n).
+ * out: real [hi, lo]; complex [re hi, re lo, im hi, im lo].
+ */
+int oracle_ryser_real_range(const double* A, int n, int ld, uint64_t k0, uint64_t count,
+                            int nthreads, double* out) {
+  if (n < 1 || n > 62 || ld < n) return -1;
+  if (k0 > (1ull << n) || count > (1ull << n) - k0) return -1;
+  ryser_job proto, jobs[ORACLE_MAX_THREADS];
+  memset(&proto, 0, sizeof proto);
+  proto.A = A;
+  proto.n = n;
+  proto.ld = ld;
+  int T = 0;
+  run_ryser(&proto, k0, count, nthreads, ryser_real_worker, jobs, &T);
+  kahan_ld S = {0.0L, 0.0L};
+  for (int t = 0; t < T; ++t) kahan_add(&S, jobs[t].re);
+  ld_to_pair(S.s, out);
+  return 0;
+}
+
+int oracle_ryser_complex_range(const double* A, int n, int ld, uint64_t k0, uint64_t count,
+                               int nthreads, double* out) {
+  if (n < 1 || n > 62 || ld < n) return -1;
+  if (k0 > (1ull << n) || count > (1ull << n) - k0) return -1;
+  ryser_job proto, jobs[ORACLE_MAX_THREADS];
+  memset(&proto, 0, sizeof proto);
+  proto.A = A;
+  proto.n = n;
+  proto.ld = ld;
+  proto.is_complex = 1;
+  int T = 0;
+  run_ryser(&proto, k0, count, nthreads, ryser_complex_worker, jobs, &T);
+  kahan_ld Sr = {0.0L, 0.0L}, Si = {0.0L, 0.0L};
+  for (int t = 0; t < T; ++t) {
+    kahan_add(&Sr, jobs[t].re);
+    kahan_add(&Si, jobs[t].im);
+  }
+  ld_to_pair(Sr.s, out);
+  ld_to_pair(Si.s, out + 2);
+  return 0;
+}
+
+/* out: [low, high] words of the partial sum modulo 2^128. */
+int oracle_ryser_int_range(const uint8_t* B, int n, int ld, uint64_t k0, uint64_t count,
+                           int nthreads, uint64_t* out) {
+  if (n < 1 || n > 62 || ld < n) return -1;
+  if (k0 > (1ull << n) || count > (1ull << n) - k0) return -1;
+  ryser_job proto, jobs[ORACLE_MAX_THREADS];
+  memset(&proto, 0, sizeof proto);
+  proto.B = B;
+  proto.n = n;
+  proto.ld = ld;
+  int T = 0;
+  run_ryser(&proto, k0, count, nthreads, ryser_int_worker, jobs, &T);
+  u128 S = 0;
+  for (int t = 0; t < T; ++t) S += jobs[t].acc;
+  u128_to_pair(S, out);
+  return 0;
+}
+
+/* per(A) = (-1)^n * sum over all 2^n subsets (Sec. II.A, Eq. ryser). */
+int oracle_ryser_real(const double* A, int n, int ld, int nthreads, double* out) {
+  if (n == 0) {
+    out[0] = 1.0;
+    out[1] = 0.0;
+    return 0;
+  }
+  if (n > 40) return -1;
+  int rc = oracle_ryser_real_range(A, n, ld, 0, 1ull << n, nthreads, out);
+  if (rc == 0 && (n & 1)) {
+    out[0] = -out[0];
+    out[1] = -out[1];
+  }
+  return rc;
+}
+
+int oracle_ryser_complex(const double* A, int n, int ld, int nthreads, double* out) {
+  if (n == 0) {
+    out[0] = 1.0;
+    out[1] = out[2] = out[3] = 0.0;
+    return 0;
+  }
+  if (n > 40) return -1;
+  int rc = oracle_ryser_complex_range(A, n, ld, 0, 1ull << n, nthreads, out);
+  if (rc == 0 && (n & 1))
+    for (int q = 0; q < 4; ++q) out[q] = -out[q];
+  return rc;
+}
+
+int oracle_ryser_int(const uint8_t* B, int n, int ld, int nthreads, uint64_t* out) {
+  if (n == 0) {
+    out[0] = 1;
+    out[1] = 0;
+    return 0;
+  }
+  if (n > 40) return -1;
+  uint64_t tmp[2];
+  int rc = oracle_ryser_int_range(B, n, ld, 0, 1ull << n, nthreads, tmp);
+  if (rc != 0) return rc;
+  u128 S = ((u128)tmp[1] << 64) | tmp[0];
+  if (n & 1) S = (u128)0 - S;
+  u128_to_pair(S, out);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O4: half-range partial sums of App. A, every term formed directly         */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  const double* A;
+  const uint8_t* B;
+  int n, ld;
+  uint64_t g0, len;
+  long double re, im;
+  u128 acc;
+} chunk_job;
+
+/* Row-sum vector of App. A (subpermanent, steps 5-7) for Gray code x:
+ *   w_i = a_{i,n} - 1/2 sum_{j=1..n} a_{ij} + sum_{j<n, x_j = 1} a_{ij}
+ * (columns and bits 0-based here: bit j of x stands for column j). */
+static void* chunk_real_worker(void* arg) {
+  chunk_job* jb = (chunk_job*)arg;
+  const int n = jb->n, ld = jb->ld;
+  kahan_ld S = {0.0L, 0.0L};
+  for (uint64_t g = jb->g0; g < jb->g0 + jb->len; ++g) {
+    uint64_t x = gray(g);
+    long double p = 1.0L;
+    for (int i = 0; i < n; ++i) {
+      long double half = 0.0L;
+      for (int j = 0; j < n; ++j) half += (long double)jb->A[i + (size_t)j * ld];
+      long double w = (long double)jb->A[i + (size_t)(n - 1) * ld] - 0.5L * half;
+      for (int j = 0; j < n - 1; ++j)
+        if ((x >> j) & 1) w += (long double)jb->A[i + (size_t)j * ld];
+      p *= w;
+    }
+    /* term g carries t = (-1)^(g+1) (App. A: nextset negates t before S += t p) */
+    kahan_add(&S, (g & 1) ? p : -p);
+  }
+  jb->re = S.s;
+  return NULL;
+}
+
+static void* chunk_complex_worker(void* arg) {
+  chunk_job* jb = (chunk_job*)arg;
+  const int n = jb->n, ld = jb->ld;
+  kahan_ld Sr = {0.0L, 0.0L}, Si = {0.0L, 0.0L};
+  for (uint64_t g = jb->g0; g < jb->g0 + jb->len; ++g) {
+    uint64_t x = gray(g);
+    long double pr = 1.0L, pi = 0.0L;
+    for (int i = 0; i < n; ++i) {
+      long double hr = 0.0L, hi = 0.0L;
+      for (int j = 0; j < n; ++j) {
+        size_t o = 2 * (i + (size_t)j * ld);
+        hr += (long double)jb->A[o];
+        hi += (long double)jb->A[o + 1];
+      }
+      size_t on = 2 * (i + (size_t)(n - 1) * ld);
+      long double wr = (long double)jb->A[on] - 0.5L * hr;
+      long double wi = (long double)jb->A[on + 1] - 0.5L * hi;
+      for (int j = 0; j < n - 1; ++j)
+        if ((x >> j) & 1) {
+          size_t o = 2 * (i + (size_t)j * ld);
+          wr += (long double)jb->A[o];
+          wi += (long double)jb->A[o + 1];
+        }
+      long double nr = pr * wr - pi * wi;
+      long double ni = pr * wi + pi * wr;
+      pr = nr;
+      pi = ni;
+    }
+    if (!(g & 1)) {
+      pr = -pr;
+      pi = -pi;
+    }
+    kahan_add(&Sr, pr);
+    kahan_add(&Si, pi);
+  }
+  jb->re = Sr.s;
+  jb->im = Si.s;
+  return NULL;
+}
+
+/* Integer form: r_i = 2 w_i is an integer, the sum is kept modulo 2^128.
+ * sum_g (-1)^(g+1) prod_i r_i = 2^n * (App. A partial sum). */
+static void* chunk_int_worker(void* arg) {
+  chunk_job* jb = (chunk_job*)arg;
+  const int n = jb->n, ld = jb->ld;
+  u128 S = 0;
+  for (uint64_t g = jb->g0; g < jb->g0 + jb->len; ++g) {
+    uint64_t x = gray(g);
+    u128 p = 1;
+    for (int i = 0; i < n; ++i) {
+      int64_t rowsum = 0;
+      for (int j = 0; j < n; ++j) rowsum += jb->B[i + (size_t)j * ld];
+      int64_t r = 2 * (int64_t)jb->B[i + (size_t)(n - 1) * ld] - rowsum;
+      for (int j = 0; j < n - 1; ++j)
+        if ((x >> j) & 1) r += 2 * (int64_t)jb->B[i + (size_t)j * ld];
+      p *= (u128)(__int128)r;
+    }
+    if (g & 1)
+      S += p;
+    else
+      S -= p;
+  }
+  jb->acc = S;
+  return NULL;
+}
+
+static int run_chunks(chunk_job* proto, uint64_t g0, uint64_t count, int nthreads,
+                      void* (*worker)(void*), chunk_job* jobs, int* used) {
+  int T = pick_threads(nthreads, count);
+  pthread_t th[ORACLE_MAX_THREADS];
+  for (int t = 0; t < T; ++t) {
+    jobs[t] = *proto;
+    uint64_t off, len;
+    distribute(count, (uint64_t)T, (uint64_t)t, &off, &len);
+    jobs[t].g0 = g0 + off;
+    jobs[t].len = len;
+  }
+  int started = 0;
+  for (int t = 0; t < T; ++t) {
+    if (pthread_create(&th[t], NULL, worker, &jobs[t]) != 0) break;
+    ++started;
+  }
+  for (int t = started; t < T; ++t) worker(&jobs[t]);
+  for (int t = 0; t < started; ++t) pthread_join(th[t], NULL);
+  *used = T;
+  return 0;
+}
+
+static int chunk_args_ok(int n, int ld, uint64_t g0, uint64_t count) {
+  if (n < 1 || n > ORACLE_MAX_N || ld < n) return 0;
+  uint64_t total = (n == 64) ? (1ull << 63) : (1ull << (n - 1));
+  if (g0 > total || count > total - g0) return 0;
+  return 1;
+}
+
+/* App. A partial sum S over Gray indices [g0, g0+count); out [hi, lo]. */
+int oracle_chunk_real(const double* A, int n, int ld, uint64_t g0, uint64_t count,
+                      int nthreads, double* out) {
+  if (!chunk_args_ok(n, ld, g0, count)) return -1;
+  chunk_job proto, jobs[ORACLE_MAX_THREADS];
+  memset(&proto, 0, sizeof proto);
+  proto.A = A;
+  proto.n = n;
+  proto.ld = ld;
+  int T = 0;
+  run_chunks(&proto, g0, count, nthreads, chunk_real_worker, jobs, &T);
+  kahan_ld S = {0.0L, 0.0L};
+  for (int t = 0; t < T; ++t) kahan_add(&S, jobs[t].re);
+  ld_to_pair(S.s, out);
+  return 0;
+}
+
+int oracle_chunk_complex(const double* A, int n, int ld, uint64_t g0, uint64_t count,
+                         int nthreads, double* out) {
+  if (!chunk_args_ok(n, ld, g0, count)) return -1;
+  chunk_job proto, jobs[ORACLE_MAX_THREADS];
+  memset(&proto, 0, sizeof proto);
+  proto.A = A;
+  proto.n = n;
+  proto.ld = ld;
+  int T = 0;
+  run_chunks(&proto, g0, count, nthreads, chunk_complex_worker, jobs, &T);
+  kahan_ld Sr = {0.0L, 0.0L}, Si = {0.0L, 0.0L};
+  for (int t = 0; t < T; ++t) {
+    kahan_add(&Sr, jobs[t].re);
+    kahan_add(&Si, jobs[t].im);
+  }
+  ld_to_pair(Sr.s, out);
+  ld_to_pair(Si.s, out + 2);
+  return 0;
+}
+
+/* out [low, high] of sum_g (-1)^(g+1) prod_i r_i modulo 2^128, r = 2w. */
+int oracle_chunk_int(const uint8_t* B, int n, int ld, uint64_t g0, uint64_t count,
+                     int nthreads, uint64_t* out) {
+  if (!chunk_args_ok(n, ld, g0, count)) return -1;
+  chunk_job proto, jobs[ORACLE_MAX_THREADS];
+  memset(&proto, 0, sizeof proto);
+  proto.B = B;
+  proto.n = n;
+  proto.ld = ld;
+  int T = 0;
+  run_chunks(&proto, g0, count, nthreads, chunk_int_worker, jobs, &T);
+  u128 S = 0;
+  for (int t = 0; t < T; ++t) S += jobs[t].acc;
+  u128_to_pair(S, out);
+  return 0;
+}
+
+/* Number of worker threads a call with nthreads <= 0 would use. */
+int oracle_default_threads(void) { return pick_threads(0, ~0ull); }

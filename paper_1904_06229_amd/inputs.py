@@ -1,0 +1,114 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module holds no permanent arithmetic: it only draws matrices.  It is
+the one piece that both the GPU path (benchmarks, tests) and the CPU oracle's
+tests use, so both sides see bit-identical inputs for a given seed.
+
+Random numbers come from numpy's PCG64 generator (the paper names only the
+Box-Muller method for its Gaussians, Sec. III; the generator is a free
+choice, and these draws are as good).
+
+Matrices are returned as numpy arrays in natural (row, column) indexing; the
+callers lay them out column-major when they hand them to a library.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def complex_gaussian(n: int, seed: int, scale: float = 1.0) -> np.ndarray:
+    """Ginibre entries (g1 + i g2)/sqrt(2), g1, g2 iid N(0,1) (Sec. III), times ``scale``.
+
+    With scale = n**-0.5 the real and imaginary parts are iid N(0, 1/(2n)).
+    """
+    r = rng(seed)
+    g = r.standard_normal((n, n, 2))
+    return (g[..., 0] + 1j * g[..., 1]) * (scale / np.sqrt(2.0))
+
+
+def real_gaussian(n: int, seed: int, scale: float = 1.0) -> np.ndarray:
+    """iid N(0, scale^2) real entries."""
+    return rng(seed).standard_normal((n, n)) * scale
+
+
+def bernoulli01(n: int, seed: int, p: float = 0.5) -> np.ndarray:
+    """iid Bernoulli(p) 0/1 entries as uint8."""
+    return (rng(seed).random((n, n)) < p).astype(np.uint8)
+
+
+def haar_columns(m: int, n: int, r: np.random.Generator) -> np.ndarray:
+    """First n columns of an m x m Haar-random unitary (Sec. VI).
+
+    QR of a complex Gaussian matrix, then each column of Q multiplied by the
+    phase r_jj/|r_jj| of R's diagonal (the Mezzadri recipe the paper uses).
+    The first n columns of QR(G)'s Q only depend on the first n columns of G,
+    so a thin QR of an m x n Gaussian gives them exactly.
+    """
+    g = r.standard_normal((m, n, 2))
+    G = (g[..., 0] + 1j * g[..., 1]) / np.sqrt(2.0)
+    Q, R = np.linalg.qr(G, mode="reduced")
+    d = np.diagonal(R)
+    ph = d / np.abs(d)
+    return Q * ph[None, :]
+
+
+def haar_block(n: int, m: int, seed: int) -> np.ndarray:
+    """Top-left n x n block U_n of an m x m Haar unitary (unscaled; Sec. VI)."""
+    return haar_columns(m, n, rng(seed))[:n, :]
+
+
+def haar_unitary(n: int, seed: int) -> np.ndarray:
+    """A full n x n Haar-random unitary."""
+    return haar_columns(n, n, rng(seed))
+
+
+def batched_haar_blocks(count: int, n_lo: int, n_hi: int, seed: int):
+    """``count`` matrices, n uniform on {n_lo..n_hi}, each the n x n top-left
+    block of an n^2-mode Haar unitary (the paper's S(n^a, n) family at a=2,
+    unscaled).  Returns (list_of_sizes, list_of_matrices)."""
+    r = rng(seed)
+    sizes = r.integers(n_lo, n_hi + 1, size=count)
+    mats = []
+    for n in sizes:
+        n = int(n)
+        mats.append(haar_columns(n * n, n, r)[:n, :])
+    return [int(s) for s in sizes], mats
+
+
+# ---- structured matrices with closed-form permanents -----------------------
+
+def ones(n: int) -> np.ndarray:
+    return np.ones((n, n), dtype=np.uint8)
+
+
+def derangement_matrix(n: int) -> np.ndarray:
+    """J - I: its permanent counts derangements."""
+    return (np.ones((n, n)) - np.eye(n)).astype(np.uint8)
+
+
+def menage_matrix(n: int) -> np.ndarray:
+    """J - I - P (P the cyclic shift): its permanent is the menage number."""
+    M = np.ones((n, n)) - np.eye(n) - np.roll(np.eye(n), 1, axis=1)
+    return M.astype(np.uint8)
+
+
+def tridiagonal_ones(n: int) -> np.ndarray:
+    """1 where |i-j| <= 1: its permanent is the Fibonacci number F_{n+1}."""
+    i = np.arange(n)
+    return (np.abs(i[:, None] - i[None, :]) <= 1).astype(np.uint8)
+
+
+def block_diag(*blocks) -> np.ndarray:
+    dt = np.result_type(*blocks)
+    n = sum(b.shape[0] for b in blocks)
+    M = np.zeros((n, n), dtype=dt)
+    o = 0
+    for b in blocks:
+        k = b.shape[0]
+        M[o:o + k, o:o + k] = b
+        o += k
+    return M
