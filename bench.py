@@ -1,0 +1,165 @@
+"""Benchmark of the Gray-code permanent on one MI355X.
+
+Default workload: one 30x30 0/1 matrix with iid Bernoulli(1/2) entries (seed
+20190413), exact permanent (2^29 Gray terms).  A step is one full library
+call: staging, the walk over all 2^(n-1) terms, the fixed-order reduction and
+the copy of the result to the host; the matrix is resident in HBM before the
+timed region starts.  The metric counts n * 2^(n-1) element-steps per
+permanent.
+
+Printed: one JSON line with the throughput, the roofline of the walk kernel
+(VALU lane-operations of the algorithm per second against the chip's vector
+issue peak; the kernel's own duration comes from HIP events recorded by the
+library on the launch stream), and the CPU oracle timed on the host cores.
+
+Other workloads (--workload c1|c3|c5|c4) are for manual runs.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 64 VALU lanes x 2.4 GHz = 3.93e13 lane-operations/s (FP64 add,
+# mul and fma each take one slot; 78.6 TFLOP/s counts an fma as two flops).
+PEAK_LANE_OPS = 256 * 64 * 2.4e9
+
+SEED_C2 = 20190413
+
+
+def algorithmic_ops_per_term(kind: str, n: int) -> int:
+    """VALU lane-operations the method needs per Gray term (App. A, subpermanent):
+    n row-sum updates, n-1 multiplies, 1 signed accumulate (complex: 2n updates,
+    n-1 complex multiplies of 4 ops, 2 accumulates)."""
+    if kind == "complex":
+        return 2 * n + 4 * (n - 1) + 2
+    return 2 * n
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c5"])
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--blocks", type=int, default=0)
+    p.add_argument("--log2-chunk", type=int, default=0)
+    p.add_argument("--precision", default="dd")
+    return p.parse_args()
+
+
+def make_workload(name):
+    from paper_1904_06229_amd import inputs
+    if name == "c1":
+        n = 20
+        return "complex", n, inputs.complex_gaussian(n, 20190401, scale=n ** -0.5), \
+            "20x20 complex128 Ginibre/sqrt(n), seed 20190401"
+    if name == "c2":
+        n = 30
+        return "int01", n, inputs.bernoulli01(n, SEED_C2), \
+            f"30x30 0/1 Bernoulli(1/2), seed {SEED_C2}, exact (int128)"
+    if name == "c3":
+        n = 40
+        return "complex", n, inputs.haar_block(n, n * n, 20190402), \
+            "40x40 top-left block of a 1600-mode Haar unitary, seed 20190402"
+    if name == "c5":
+        n = 48
+        return "real", n, inputs.real_gaussian(n, 20190403), "48x48 real N(0,1), seed 20190403"
+    raise ValueError(name)
+
+
+def cpu_baseline(kind, n, A):
+    """The oracle, as it stands, on a bounded sample of the same workload."""
+    import oracle
+    oracle.build(force=False)
+    threads = oracle.default_threads()
+    if kind == "int01":
+        # Ryser over a prefix of the 2^n subsets, sized to ~10-20 s on the host.
+        count = 1 << n if n <= 30 else 1 << 30
+        t0 = time.perf_counter()
+        oracle.ryser_range(A, 0, count, threads=threads)
+        dt = time.perf_counter() - t0
+        frac = count / float(1 << n)
+        sample = f"integer Ryser over {count} of the 2^{n} subsets ({frac:.3g} of one permanent)"
+    else:
+        # direct half-range terms (O(n^2) each) over a prefix of the Gray range
+        count = 1 << 14
+        t0 = time.perf_counter()
+        oracle.chunk_partial(A, 0, count, threads=threads)
+        dt = time.perf_counter() - t0
+        frac = count / float(1 << (n - 1))
+        sample = f"{count} Gray terms formed directly (long double), {frac:.3g} of one permanent"
+    value = frac * n * 2.0 ** (n - 1) / dt
+    return {"value": value, "unit": "n*2^(n-1)/s", "cores": threads, "kind": "oracle",
+            "sample": sample, "seconds": round(dt, 3)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1904_06229_amd import binding as B
+
+    kind, n, A, desc = make_workload(args.workload)
+    dA = torch.from_numpy(np.ascontiguousarray(A)).to("cuda")
+    fn = {"int01": B.perm_int01, "real": B.perm_real, "complex": B.perm_complex}[kind]
+    kw = dict(blocks=args.blocks, log2_chunk=args.log2_chunk)
+    if kind != "int01":
+        kw["precision"] = args.precision
+    for _ in range(args.warmup):
+        r = fn(dA, **kw)
+    torch.cuda.synchronize()
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = fn(dA, **kw)
+        kms.append(r.kernel_ms)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    per_perm = n * 2.0 ** (n - 1)
+    value = args.steps * per_perm / dt
+    kavg = sum(kms) / len(kms)
+    alg = algorithmic_ops_per_term(kind, n) * 2.0 ** (n - 1)
+    achieved = alg / (kavg * 1e-3)
+    out = {
+        "metric": "Gray-code terms/sec (n*2^(n-1)/s)",
+        "value": value,
+        "unit": "n*2^(n-1)/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 exact-integer + i64 bins" if kind == "int01" else "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "n": n, "terms": 2 ** (n - 1), "log2_chunk": r.log2_chunk,
+                   "blocks": r.blocks},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                     "unit": "TOP/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                     "kernel": f"walk_{kind}_kernel<{n}>", "kernel_ms": kavg,
+                     "ops_per_launch": alg},
+    }
+    if kind == "int01":
+        out["result"] = str(r.exact)
+    else:
+        out["result"] = repr(r.value)
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(kind, n, A)
+        out["cpu_baseline"] = cb
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

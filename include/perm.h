@@ -1,0 +1,207 @@
+/*
+ * perm.h -- exact matrix permanents on AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates the permanent of a dense n x n real, complex or 0/1
+ * matrix (Lundow & Markstrom, Sec. I, Eq. per) with the half-range,
+ * Gray-code-ordered form of Ryser's inclusion-exclusion (Sec. II.A: Ryser's
+ * formula, Eq. ryser, visited in Gray order and halved by pinning the last
+ * column; App. A: distribute, Gray unranking, nextset, subpermanent,
+ * permanent).  In the notation of App. A, for the Gray code x = gray(g) of a
+ * term index g in [0, 2^(n-1)),
+ *
+ *     w_i(x) = a_{i,n} - 1/2 sum_{j=1..n} a_{ij} + sum_{j<n, x_j=1} a_{ij},
+ *     S      = sum_g (-1)^(g+1) prod_i w_i(gray(g)),
+ *     per(A) = 2 (-1)^n S.
+ *
+ * Conventions shared by every entry point:
+ *   - Matrices are caller-owned DEVICE memory, column-major with leading
+ *     dimension ld >= n: a(i,j) = A[i + j*ld].  Complex matrices are
+ *     interleaved (re, im) doubles: a(i,j) = A[2(i+j*ld)] + i A[2(i+j*ld)+1].
+ *     Since per(A) = per(A^T), a row-major caller may pass its array as is.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  All work is
+ *     enqueued on it.  Single-matrix calls wait for that stream and return a
+ *     host value; perm_batched only enqueues and returns at once.
+ *   - No pointer is kept after a call returns.  Library-owned device
+ *     workspace (staged matrix, partial sums, queue) is allocated lazily per
+ *     device and kept until perm_release().  Calls that overlap on one device
+ *     (several host threads, or several streams) are not supported.
+ *   - Errors are reported only through the returned status; on error the
+ *     outputs are left untouched.  perm_last_error() has a text message.
+ *   - n = 0 gives per = 1 (the empty product).  n <= 64.
+ */
+#ifndef PERM_H
+#define PERM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PERM_OK = 0,
+  PERM_EINVAL = 1,     /* bad n, ld, option, range, or (0/1 path) an entry not 0 or 1 */
+  PERM_ERANGE = 2,     /* 0/1 path: the exact result might not fit 128 bits (see perm_int01) */
+  PERM_ENONFINITE = 3, /* a NaN or infinity in A */
+  PERM_ENOMEM = 4,     /* device or pinned host allocation failed */
+  PERM_EHIP = 5,       /* HIP runtime error (text in perm_last_error) */
+  PERM_ENOTIMPL = 6    /* option combination not provided */
+} perm_status;
+
+/* Arithmetic of the Gray walk (App. A, subpermanent; Sec. II.B, Precision). */
+typedef enum {
+  PERM_FP64_DD = 0,  /* FP64 row sums and products, per-lane double-double sum (default;
+                        the analogue of the paper's Kahan / double-quad summation) */
+  PERM_FP64 = 1,     /* FP64 row sums, products and plain FP64 sum (the paper's "double") */
+  PERM_SPLIT_F32 = 2 /* FP64 row sums, FP32 products, double-double sum */
+} perm_precision;
+
+/* Options.  A zeroed struct (or NULL) selects the defaults. */
+typedef struct {
+  int32_t precision;      /* perm_precision; ignored by perm_int01 */
+  int32_t log2_chunk;     /* Gray terms per lane chunk = 2^log2_chunk; 0 = automatic.
+                             Every chunk's row sums are formed afresh from A, so this
+                             bounds the walk's drift.  Max 24 (0/1 path: 10). */
+  int32_t drift_check;    /* 1: at every chunk end re-form the row sums from A and report
+                             the largest |w_walked - w_fresh| / (1/2 sum_j |a_ij|) */
+  int32_t no_row_scaling; /* 1: do not scale rows by powers of two (scaling is exact and
+                             undone at the end; it keeps FP32 products in range) */
+  int32_t blocks;         /* workgroups of the walk kernel; 0 = automatic */
+  int32_t use_graph;      /* perm_batched: replay a captured HIP graph when the same
+                             arguments come again (1) or launch directly (0) */
+  int32_t reserved[2];    /* must be 0 */
+} perm_opts;
+
+/* Result of a single-matrix call. */
+typedef struct {
+  double re_hi, re_lo;   /* real part as the unevaluated sum re_hi + re_lo */
+  double im_hi, im_lo;   /* imaginary part (0 for real and 0/1 input) */
+  uint64_t int_lo;       /* 0/1 path: exact value, two's-complement 128-bit (low word) */
+  int64_t int_hi;        /*                                              (high word) */
+  double max_drift;      /* drift_check: largest relative row-sum drift; otherwise -1 */
+  uint64_t terms;        /* Gray terms summed */
+  uint64_t chunks;       /* lane chunks walked (including single-term ragged ends) */
+  int32_t log2_chunk;    /* chunk length used */
+  int32_t blocks;        /* workgroups of the main walk launch */
+  float kernel_ms;       /* duration of the walk launches, from HIP events on `stream` */
+  float total_ms;        /* duration of the whole call on `stream` (staging to result) */
+} perm_result;
+
+/*
+ * perm_real -- per(A) of a real n x n matrix (FP64 input).
+ *   dA      device pointer, column-major, leading dimension ld >= max(n,1).
+ *   out     host pointer; value in re_hi + re_lo (relative error of the default
+ *           precision: about 1e-15..1e-11 depending on cancellation; see docs).
+ * Errors: PERM_EINVAL (n < 0, n > 64, ld < n, bad opts), PERM_ENONFINITE, PERM_EHIP.
+ */
+perm_status perm_real(const double* dA, int n, int ld, const perm_opts* opts,
+                      perm_result* out, void* stream);
+
+/*
+ * perm_complex -- per(A) of a complex n x n matrix (interleaved complex128).
+ *   Value in (re_hi + re_lo) + i (im_hi + im_lo).  Errors as perm_real.
+ */
+perm_status perm_complex(const double* dA, int n, int ld, const perm_opts* opts,
+                         perm_result* out, void* stream);
+
+/*
+ * perm_int01 -- exact per(A) of a 0/1 matrix (one byte per entry, each 0 or 1).
+ *   The walk keeps the doubled row sums r_i = 2 w_i, which are small integers,
+ *   and sums sum_g (-1)^(g+1) prod_i r_i = (-1)^n 2^(n-1) per(A) exactly modulo
+ *   2^128 (the row sums are exact integers held in FP64 registers; products are
+ *   formed exactly in row groups whose bound stays below 2^50 and combined with
+ *   error-free transformations into 51-bit integer bins).  The result is exact
+ *   when 2^(n-1) per(A) < 2^127; the library checks the sufficient condition
+ *   (n-1) + sum_i log2(d_i!)/d_i < 127 (Bregman's bound, d_i = row sums) on the
+ *   device before the walk and returns PERM_ERANGE otherwise (always passes for
+ *   n <= 28).  Value in int_lo/int_hi; re_hi + re_lo holds its nearest double pair.
+ * Errors: PERM_EINVAL (sizes, or an entry other than 0/1), PERM_ERANGE, PERM_EHIP.
+ */
+perm_status perm_int01(const uint8_t* dA, int n, int ld, const perm_opts* opts,
+                       perm_result* out, void* stream);
+
+/* Element types for perm_partial. */
+typedef enum { PERM_DT_REAL = 0, PERM_DT_COMPLEX = 1, PERM_DT_INT01 = 2 } perm_dtype;
+
+/*
+ * perm_partial -- the paper's subpermanent (App. A) over an explicit range:
+ *   S = sum_{g=start}^{start+count-1} (-1)^(g+1) prod_i w_i(gray(g)),
+ *   0 <= start, start + count <= 2^(n-1), n >= 1.  No final factor 2(-1)^n and
+ *   no row-scaling factor is applied: the value refers to A itself.  For
+ *   PERM_DT_INT01 the integer form sum_g (-1)^(g+1) prod_i (2 w_i) is returned
+ *   exactly modulo 2^128 in int_lo/int_hi (= 2^n S; no range check is made).
+ *   Ranges need not be aligned; unaligned ends are summed one term per lane.
+ *   Splitting [0, 2^(n-1)) into pieces and adding the partials gives the
+ *   permanent (how the range would be divided between devices).
+ */
+perm_status perm_partial(int dtype, const void* dA, int n, int ld, uint64_t start,
+                         uint64_t count, const perm_opts* opts, perm_result* out,
+                         void* stream);
+
+/*
+ * perm_batched -- permanents of many independent matrices in one persistent
+ * launch (the random-matrix studies of Secs. III-VI compute many
+ * independent permanents).
+ *   dA       device array holding the matrices back to back; matrix m starts at
+ *            element offset h_offset[m] (in doubles) and is column-major with
+ *            ld = n_m (complex: interleaved pairs, offset still in doubles).
+ *   h_n      HOST array of the sizes, 1 <= n_m <= 32.
+ *   h_offset HOST array of offsets.
+ *   count    number of matrices (0 is allowed and does nothing).
+ *   d_out    device array, 4 doubles per matrix: re_hi, re_lo, im_hi, im_lo.
+ *   d_status device array of count int32 (may be NULL): PERM_OK or PERM_ENONFINITE.
+ * Work is bucketed by n (largest first), cut into wave-sized items of
+ * 2^log2_chunk-term lane chunks (per-n lengths from the autotuner unless
+ * opts->log2_chunk is set), and pulled from a device queue by a persistent
+ * kernel.  Enqueued on `stream`; returns without waiting.
+ */
+perm_status perm_batched(const double* dA, const int32_t* h_n, const int64_t* h_offset,
+                         int count, int is_complex, const perm_opts* opts, double* d_out,
+                         int32_t* d_status, void* stream);
+
+/*
+ * perm_autotune -- time candidate chunk lengths for the batched path on
+ * synthetic matrices of each size in [n_lo, n_hi] (1 <= n_lo <= n_hi <= 32) and
+ * keep the fastest per size for later perm_batched calls.  If cache_path is not
+ * NULL the table is also written there as JSON (and perm_batched reads it back
+ * when PERM_AUTOTUNE_CACHE names that file).  Waits for `stream`.
+ */
+perm_status perm_autotune(int is_complex, int n_lo, int n_hi, const char* cache_path,
+                          void* stream);
+
+/* Chunk plan for a Gray-index range, computed on the host (no GPU needed). */
+typedef struct {
+  int32_t log2_chunk;      /* L = 2^log2_chunk */
+  uint64_t head_start, head_count;   /* unaligned leading terms, one term per lane */
+  uint64_t body_first_chunk;         /* body = chunks [first, first+body_chunks) of length L */
+  uint64_t body_chunks;
+  uint64_t tail_start, tail_count;   /* unaligned trailing terms */
+  uint64_t body_tasks;               /* wave tasks (64 lanes each) covering the body */
+} perm_plan_info;
+
+/*
+ * perm_plan -- the decomposition the library uses for [start, start+count) at
+ * size n (App. A distribute, with power-of-two aligned chunks instead of m
+ * equal parts).  log2_chunk = 0 picks automatically; is_int01 caps it at 10.
+ * Returns PERM_EINVAL for an invalid range.  Host only.
+ */
+perm_status perm_plan(int n, uint64_t start, uint64_t count, int log2_chunk, int is_int01,
+                      perm_plan_info* out);
+
+/*
+ * perm_int01_bound -- log2 of the 0/1 path's accumulator bound,
+ * (n-1) + sum_i log2(d_i!)/d_i for row sums d_i (rows with d_i = 0 make the
+ * permanent 0 and the bound 0).  Host only; the device check uses the same rule.
+ */
+double perm_int01_bound(const int32_t* row_degrees, int n);
+
+const char* perm_strerror(perm_status s);  /* static text for a status */
+const char* perm_last_error(void);         /* text of the last failure on this thread */
+const char* perm_version(void);
+void perm_release(void);                   /* free library-owned workspace on all devices */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PERM_H */

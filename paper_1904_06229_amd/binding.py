@@ -1,0 +1,272 @@
+"""Python binding of libperm.so: argument marshalling only.
+
+Every function here has the name of the C entry point it calls (see
+``include/perm.h``) and does nothing but check Python-side arguments, take
+device pointers and the current HIP stream from torch tensors, and call the
+library through ctypes.  Every step of the computation runs in the library's
+HIP kernels; there is no fallback.  If ``libperm.so`` has not been built the
+import fails with an error that says so.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libperm.so")
+
+PERM_OK, PERM_EINVAL, PERM_ERANGE, PERM_ENONFINITE, PERM_ENOMEM, PERM_EHIP, PERM_ENOTIMPL = range(7)
+PERM_FP64_DD, PERM_FP64, PERM_SPLIT_F32 = 0, 1, 2
+PERM_DT_REAL, PERM_DT_COMPLEX, PERM_DT_INT01 = 0, 1, 2
+PRECISIONS = {"dd": PERM_FP64_DD, "fp64": PERM_FP64, "split": PERM_SPLIT_F32}
+
+
+class perm_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("log2_chunk", ctypes.c_int32),
+                ("drift_check", ctypes.c_int32), ("no_row_scaling", ctypes.c_int32),
+                ("blocks", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
+class perm_result(ctypes.Structure):
+    _fields_ = [("re_hi", ctypes.c_double), ("re_lo", ctypes.c_double),
+                ("im_hi", ctypes.c_double), ("im_lo", ctypes.c_double),
+                ("int_lo", ctypes.c_uint64), ("int_hi", ctypes.c_int64),
+                ("max_drift", ctypes.c_double), ("terms", ctypes.c_uint64),
+                ("chunks", ctypes.c_uint64), ("log2_chunk", ctypes.c_int32),
+                ("blocks", ctypes.c_int32), ("kernel_ms", ctypes.c_float),
+                ("total_ms", ctypes.c_float)]
+
+
+class perm_plan_info(ctypes.Structure):
+    _fields_ = [("log2_chunk", ctypes.c_int32), ("head_start", ctypes.c_uint64),
+                ("head_count", ctypes.c_uint64), ("body_first_chunk", ctypes.c_uint64),
+                ("body_chunks", ctypes.c_uint64), ("tail_start", ctypes.c_uint64),
+                ("tail_count", ctypes.c_uint64), ("body_tasks", ctypes.c_uint64)]
+
+
+# Every symbol include/perm.h declares, with its ctypes signature.
+_vp, _i, _u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64
+SIGNATURES = {
+    "perm_real": ([_vp, _i, _i, ctypes.POINTER(perm_opts), ctypes.POINTER(perm_result), _vp], _i),
+    "perm_complex": ([_vp, _i, _i, ctypes.POINTER(perm_opts), ctypes.POINTER(perm_result), _vp], _i),
+    "perm_int01": ([_vp, _i, _i, ctypes.POINTER(perm_opts), ctypes.POINTER(perm_result), _vp], _i),
+    "perm_partial": ([_i, _vp, _i, _i, _u64, _u64, ctypes.POINTER(perm_opts),
+                      ctypes.POINTER(perm_result), _vp], _i),
+    "perm_batched": ([_vp, _vp, _vp, _i, _i, ctypes.POINTER(perm_opts), _vp, _vp, _vp], _i),
+    "perm_autotune": ([_i, _i, _i, ctypes.c_char_p, _vp], _i),
+    "perm_plan": ([_i, _u64, _u64, _i, _i, ctypes.POINTER(perm_plan_info)], _i),
+    "perm_int01_bound": ([ctypes.POINTER(ctypes.c_int32), _i], ctypes.c_double),
+    "perm_strerror": ([_i], ctypes.c_char_p),
+    "perm_last_error": ([], ctypes.c_char_p),
+    "perm_version": ([], ctypes.c_char_p),
+    "perm_release": ([], None),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it first (python -m paper_1904_06229_amd.build, "
+            "or __graft_entry__.build()); there is no non-GPU fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (args, res) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+class PermError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.perm_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {_lib.perm_strerror(status).decode()} ({status}): {msg}")
+
+
+@dataclass
+class Result:
+    """A permanent (or partial sum) as returned by the library."""
+
+    re_hi: float
+    re_lo: float
+    im_hi: float
+    im_lo: float
+    exact: int | None
+    max_drift: float
+    terms: int
+    chunks: int
+    log2_chunk: int
+    blocks: int
+    kernel_ms: float
+    total_ms: float
+
+    @property
+    def value(self):
+        if self.exact is not None:
+            return self.exact
+        if self.im_hi != 0.0 or self.im_lo != 0.0:
+            return complex(self.re_hi + self.re_lo, self.im_hi + self.im_lo)
+        return self.re_hi + self.re_lo
+
+
+def _result(r: perm_result, exact: bool) -> Result:
+    ex = None
+    if exact:
+        v = (r.int_lo & ((1 << 64) - 1)) | ((r.int_hi & ((1 << 64) - 1)) << 64)
+        ex = v - (1 << 128) if v >= (1 << 127) else v
+    return Result(r.re_hi, r.re_lo, r.im_hi, r.im_lo, ex, r.max_drift, r.terms, r.chunks,
+                  r.log2_chunk, r.blocks, r.kernel_ms, r.total_ms)
+
+
+def make_opts(precision="dd", log2_chunk=0, drift_check=False, row_scaling=True, blocks=0,
+              use_graph=False) -> perm_opts:
+    o = perm_opts()
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.log2_chunk = int(log2_chunk)
+    o.drift_check = 1 if drift_check else 0
+    o.no_row_scaling = 0 if row_scaling else 1
+    o.blocks = int(blocks)
+    o.use_graph = 1 if use_graph else 0
+    return o
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _matrix(A, dtype_name):
+    """(pointer, n, ld) of a square device tensor, viewed column-major.
+
+    A row-major tensor is passed as the column-major array of its transpose;
+    per(A^T) = per(A), so no copy is needed.
+    """
+    import torch
+    if not isinstance(A, torch.Tensor) or A.device.type != "cuda":
+        raise TypeError("expected a CUDA (HIP) torch tensor")
+    want = {"real": torch.float64, "complex": torch.complex128, "int01": torch.uint8}[dtype_name]
+    if A.dtype != want:
+        raise TypeError(f"expected dtype {want}, got {A.dtype}")
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("expected a square matrix")
+    n = A.shape[0]
+    if n == 0:
+        return ctypes.c_void_p(A.data_ptr() or 0), 0, 1
+    s0, s1 = A.stride()
+    if s1 == 1 and s0 >= n:
+        ld = s0
+    elif s0 == 1 and s1 >= n:
+        ld = s1
+    elif n == 1:
+        ld = 1
+    else:
+        raise ValueError("matrix must have unit stride along one dimension")
+    return ctypes.c_void_p(A.data_ptr()), n, ld
+
+
+def _check(st, where):
+    if st != PERM_OK:
+        raise PermError(st, where)
+
+
+def perm_real(A, stream=None, **opts) -> Result:
+    p, n, ld = _matrix(A, "real")
+    o, r = make_opts(**opts), perm_result()
+    _check(_lib.perm_real(p, n, ld, ctypes.byref(o), ctypes.byref(r), _stream_handle(stream)),
+           "perm_real")
+    return _result(r, False)
+
+
+def perm_complex(A, stream=None, **opts) -> Result:
+    p, n, ld = _matrix(A, "complex")
+    o, r = make_opts(**opts), perm_result()
+    _check(_lib.perm_complex(p, n, ld, ctypes.byref(o), ctypes.byref(r), _stream_handle(stream)),
+           "perm_complex")
+    return _result(r, False)
+
+
+def perm_int01(A, stream=None, **opts) -> Result:
+    p, n, ld = _matrix(A, "int01")
+    o, r = make_opts(**opts), perm_result()
+    _check(_lib.perm_int01(p, n, ld, ctypes.byref(o), ctypes.byref(r), _stream_handle(stream)),
+           "perm_int01")
+    return _result(r, True)
+
+
+def perm_partial(A, start: int, count: int, stream=None, **opts) -> Result:
+    """Partial sum of the terms of A itself (entry A[i, j] in row i, column j).
+
+    Unlike the full permanent, a partial sum changes under transposition, so
+    the library must see A column-major: a row-major tensor is copied to
+    column-major storage first (pass A.t().contiguous().t() to avoid it).
+    """
+    import torch
+    kind = {torch.float64: "real", torch.complex128: "complex", torch.uint8: "int01"}[A.dtype]
+    dt = {"real": PERM_DT_REAL, "complex": PERM_DT_COMPLEX, "int01": PERM_DT_INT01}[kind]
+    if A.dim() == 2 and A.shape[0] > 1 and A.stride(0) != 1:
+        A = A.t().contiguous().t()
+    p, n, ld = _matrix(A, kind)
+    o, r = make_opts(**opts), perm_result()
+    _check(_lib.perm_partial(dt, p, n, ld, int(start), int(count), ctypes.byref(o),
+                             ctypes.byref(r), _stream_handle(stream)), "perm_partial")
+    return _result(r, kind == "int01")
+
+
+def perm_batched(A_packed, sizes, offsets, is_complex: bool, out, status=None, stream=None,
+                 **opts) -> None:
+    """Enqueue the batched permanents; results land in ``out`` (float64, 4 per matrix)."""
+    import torch
+    count = len(sizes)
+    n_arr = (ctypes.c_int32 * max(count, 1))(*[int(x) for x in sizes])
+    o_arr = (ctypes.c_int64 * max(count, 1))(*[int(x) for x in offsets])
+    o = make_opts(**opts)
+    if A_packed.dtype != torch.float64 or out.dtype != torch.float64:
+        raise TypeError("A_packed and out must be float64 (complex data as interleaved pairs)")
+    if out.numel() < 4 * count:
+        raise ValueError("out needs 4 doubles per matrix")
+    st_ptr = ctypes.c_void_p(status.data_ptr()) if status is not None else ctypes.c_void_p(0)
+    _check(_lib.perm_batched(ctypes.c_void_p(A_packed.data_ptr()), n_arr, o_arr, count,
+                             1 if is_complex else 0, ctypes.byref(o),
+                             ctypes.c_void_p(out.data_ptr()), st_ptr, _stream_handle(stream)),
+           "perm_batched")
+
+
+def perm_autotune(is_complex: bool, n_lo: int, n_hi: int, cache_path: str | None = None,
+                  stream=None) -> None:
+    cp = cache_path.encode() if cache_path else None
+    _check(_lib.perm_autotune(1 if is_complex else 0, n_lo, n_hi, cp, _stream_handle(stream)),
+           "perm_autotune")
+
+
+def perm_plan(n: int, start: int, count: int, log2_chunk: int = 0, is_int01: bool = False) -> dict:
+    p = perm_plan_info()
+    _check(_lib.perm_plan(n, start, count, log2_chunk, 1 if is_int01 else 0, ctypes.byref(p)),
+           "perm_plan")
+    return {f: getattr(p, f) for f, _ in perm_plan_info._fields_}
+
+
+def perm_int01_bound(degrees) -> float:
+    d = (ctypes.c_int32 * max(len(degrees), 1))(*[int(x) for x in degrees])
+    return _lib.perm_int01_bound(d, len(degrees))
+
+
+def perm_strerror(status: int) -> str:
+    return _lib.perm_strerror(status).decode()
+
+
+def perm_last_error() -> str:
+    return _lib.perm_last_error().decode()
+
+
+def perm_version() -> str:
+    return _lib.perm_version().decode()
+
+
+def perm_release() -> None:
+    _lib.perm_release()

@@ -1,0 +1,269 @@
+// Exact Gray-code walk for 0/1 matrices.
+//
+// The walk keeps r_i = 2 w_i (App. A, subpermanent), which for a 0/1 matrix
+// is an integer with |r_i| <= d_i <= n (d_i = row sum), and accumulates
+// sum_g (-1)^(g+1) prod_i r_i = (-1)^n 2^(n-1) per(A) exactly modulo 2^128.
+//
+// Exact arithmetic on a VALU whose fast integer multiplier is 24 bits wide:
+//   * r_i are carried in FP64 registers (exact: small integers); the update
+//     r += (+/-)2 a_ij is a v_add_f64 with an SGPR operand, as in the real walk.
+//   * Rows are multiplied in groups of k = int01_group_rows(n) rows with
+//     n^k < 2^50, so every group product G is an exact FP64 integer.
+//   * Group products are combined with error-free transformations: TwoProduct
+//     (h = G1*G2, l = fma(G1, G2, -h), G1*G2 = h + l exactly) and an exact
+//     split at 2^51 (q = h + 1.5*2^103 rounds h to a multiple of 2^51; then
+//     h - (q - 1.5*2^103) is exact, and the bit pattern of q minus that of
+//     1.5*2^103 is h's high part as an integer).  The product is carried as
+//     integer limbs of weight 1, 2^51, 2^102 held in doubles.
+//   * Limbs land in three 64-bit integer bins through their bit patterns:
+//     for |y| <= 2^51, bits(y + 1.5*2^52) - bits(1.5*2^52) = y.  The two terms
+//     of a pair enter with opposite signs, so the constant offsets cancel and
+//     only add/sub of bit patterns remains in the loop.
+//   * Bins are folded into a 128-bit sum at the end of every chunk (chunks are
+//     at most 2^10 terms, so the weight-1 and weight-2^51 bins cannot wrap).
+#include "perm_device.hpp"
+#include "perm_internal.hpp"
+
+namespace perm {
+namespace {
+
+constexpr double kC51 = 15845632502852867518708790067200.0;  // 1.5 * 2^103
+constexpr double kM52 = 6755399441055744.0;                  // 1.5 * 2^52
+constexpr double kInv51 = 1.0 / 2251799813685248.0;          // 2^-51
+
+__device__ __forceinline__ uint64_t bits(double x) { return (uint64_t)__double_as_longlong(x); }
+
+struct Bins {
+  uint64_t b0, b1, b2;  // weights 1, 2^51, 2^102 (two's complement, wrapping)
+};
+
+template <bool ADD>
+__device__ __forceinline__ void bin_put(uint64_t& bin, uint64_t v) {
+  if constexpr (ADD)
+    bin += v;
+  else
+    bin -= v;
+}
+
+// Exact product of the row sums, entered into the bins with sign ADD ? + : -.
+// The entered bit patterns carry constant offsets (bits of 1.5*2^103 or of
+// 1.5*2^52) that cancel between the + and - term of a pair.
+template <int N, bool ADD>
+__device__ __forceinline__ void term_bins(const double (&r)[N], Bins& B) {
+  constexpr int k = int01_group_rows(N);
+  constexpr int K = (N + k - 1) / k;
+  double G[K];
+#pragma unroll
+  for (int g = 0; g < K; ++g) {
+    double p = r[g * k];
+#pragma unroll
+    for (int i = g * k + 1; i < (g + 1) * k && i < N; ++i) p *= r[i];
+    G[g] = p;
+  }
+  if constexpr (K == 1) {
+    bin_put<ADD>(B.b0, bits(G[0] + kM52));
+  } else {
+    // X = G0 * G1 as limbs (X0 weight 1, X1 weight 2^51; X2 weight 2^102).
+    double X0, X1, X2 = 0.0;
+    {
+      const double h = G[0] * G[1];
+      const double l = fma(G[0], G[1], -h);
+      const double q = h + kC51;
+      const double hr = q - kC51;
+      if constexpr (K == 2) {
+        bin_put<ADD>(B.b1, bits(q));
+        bin_put<ADD>(B.b0, bits(((h - hr) + l) + kM52));
+        return;
+      }
+      X0 = (h - hr) + l;
+      X1 = hr * kInv51;
+    }
+    // Middle factors: X <- X * G mod 2^153, limbs renormalised below 2^51.
+#pragma unroll
+    for (int g = 2; g + 1 < K; ++g) {
+      double h[3], l[3], y[3], H[3];
+      const double x[3] = {X0, X1, X2};
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        h[m] = x[m] * G[g];
+        l[m] = fma(x[m], G[g], -h[m]);
+        const double q = h[m] + kC51;
+        const double hr = q - kC51;
+        y[m] = (h[m] - hr) + l[m];
+        H[m] = hr * kInv51;
+      }
+      double Y1 = y[1] + H[0];
+      double Y2 = y[2] + H[1];
+      {
+        const double q = Y1 + kC51;
+        const double hr = q - kC51;
+        Y1 = Y1 - hr;
+        Y2 = Y2 + hr * kInv51;
+      }
+      {
+        const double q = Y2 + kC51;
+        Y2 = Y2 - (q - kC51);  // keep Y2 modulo 2^51
+      }
+      X0 = y[0];
+      X1 = Y1;
+      X2 = Y2;
+    }
+    // Last factor: products of the limbs go straight into the bins.
+    const double Gl = G[K - 1];
+    {
+      const double h = X0 * Gl;
+      const double l = fma(X0, Gl, -h);
+      const double q = h + kC51;
+      const double hr = q - kC51;
+      bin_put<ADD>(B.b0, bits(((h - hr) + l) + kM52));
+      bin_put<ADD>(B.b1, bits(q));
+    }
+    {
+      const double h = X1 * Gl;
+      const double l = fma(X1, Gl, -h);
+      const double q = h + kC51;
+      const double hr = q - kC51;
+      bin_put<ADD>(B.b1, bits(((h - hr) + l) + kM52));
+      bin_put<ADD>(B.b2, bits(q));
+    }
+    if constexpr (K >= 4) {
+      const double h = X2 * Gl;
+      const double l = fma(X2, Gl, -h);
+      const double q = h + kC51;
+      const double hr = q - kC51;
+      bin_put<ADD>(B.b2, bits(((h - hr) + l) + kM52));
+    }
+  }
+}
+
+// Offsets carried by one term's entries (per bin), for single-term chunks.
+template <int N>
+__device__ __forceinline__ Bins term_offsets() {
+  constexpr int k = int01_group_rows(N);
+  constexpr int K = (N + k - 1) / k;
+  const uint64_t c = bits(kC51), m = bits(kM52);
+  if constexpr (K == 1) return Bins{m, 0, 0};
+  if constexpr (K == 2) return Bins{m, c, 0};
+  if constexpr (K == 3) return Bins{m, c + m, c};
+  return Bins{m, c + m, c + m};
+}
+
+__device__ __forceinline__ u128 fold(const Bins& B) {
+  const unsigned __int128 v0 = (unsigned __int128)(__int128)(int64_t)B.b0;
+  const unsigned __int128 v1 = (unsigned __int128)(__int128)(int64_t)B.b1;
+  const unsigned __int128 v2 = (unsigned __int128)(__int128)(int64_t)B.b2;
+  const unsigned __int128 s = v0 + (v1 << 51) + (v2 << 102);
+  return u128{(uint64_t)s, (uint64_t)(s >> 64)};
+}
+
+template <int N>
+__device__ __forceinline__ void add_col(double (&w)[N], const double* __restrict__ staged,
+                                        uint32_t sub, int j) {
+  cdptr col = as_const(staged + sub * (N * N) + j * N);
+#pragma unroll
+  for (int i = 0; i < N; ++i) w[i] += col[i];
+}
+
+// Integer-form sum of chunk G's terms, modulo 2^128.
+template <int N, bool DRIFT>
+__device__ __forceinline__ u128 walk_chunk(const double* __restrict__ staged, uint64_t G, int b,
+                                           uint32_t gpar, double& drift) {
+  double r[N];
+  form_w_real<N>(staged, G << b, r);  // staged holds +2A/-2A, so this is r = 2w
+  Bins B{0, 0, 0};
+  if (b == 0) {
+    const Bins off = term_offsets<N>();
+    if (G & 1) {
+      term_bins<N, true>(r, B);
+      B.b0 -= off.b0;
+      B.b1 -= off.b1;
+      B.b2 -= off.b2;
+    } else {
+      term_bins<N, false>(r, B);
+      B.b0 += off.b0;
+      B.b1 += off.b1;
+      B.b2 += off.b2;
+    }
+    return fold(B);
+  }
+  const uint32_t half = 1u << (b - 1);
+  uint32_t t = 0;
+  for (; t + 1 < half; ++t) {
+    term_bins<N, false>(r, B);
+    add_col<N>(r, staged, t & 1u, 0);
+    term_bins<N, true>(r, B);
+    const uint32_t s1 = 2 * t + 2;
+    const int j = __builtin_ctz(s1);
+    add_col<N>(r, staged, flip_subtracts(s1, j, b, gpar), j);
+  }
+  term_bins<N, false>(r, B);
+  add_col<N>(r, staged, (b >= 2) ? (t & 1u) : gpar, 0);
+  term_bins<N, true>(r, B);
+  if constexpr (DRIFT) {
+    // The integer walk cannot drift; the check confirms it.
+    double f[N];
+    form_w_real<N>(staged, ((G + 1) << b) - 1, f);
+#pragma unroll
+    for (int i = 0; i < N; ++i) drift = fmax(drift, fabs(r[i] - f[i]));
+  }
+  return fold(B);
+}
+
+template <int N, bool DRIFT>
+__global__ __launch_bounds__(kBlock) void walk_int01_kernel(WalkArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint64_t wave = wave_id();
+  const uint64_t nwaves = (uint64_t)gridDim.x * kWavesPerBlock;
+  u128 acc{0, 0};
+  double drift = 0.0;
+  if (a.status[0] == kStOk) {
+    for (uint64_t task = wave; task < a.ntasks; task += nwaves) {
+      const uint64_t c = task_chunk(task, lane);
+      const uint32_t gpar = (uint32_t)((a.first + (task & 1)) & 1);
+      double dr = 0.0;
+      const u128 part = walk_chunk<N, DRIFT>(a.staged, a.first + c, a.b, gpar, dr);
+      if (c < a.nchunks) {
+        acc = u128_add(acc, part);
+        drift = fmax(drift, dr);
+      }
+    }
+  }
+  const u128 v = wave_sum(acc);
+  const u128 blk = block_sum(v, u128_add);
+  uint64_t* out = (uint64_t*)a.partials;
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = blk.lo;
+    out[2 * blockIdx.x + 1] = blk.hi;
+  }
+  if (DRIFT) {
+    const double m = wave_max(drift);
+    const double bm = block_sum(m, [](double x, double y) { return fmax(x, y); });
+    if (threadIdx.x == 0) a.drift_part[blockIdx.x] = bm;
+  }
+}
+
+template <int N>
+hipError_t dispatch(bool drift, const WalkArgs& a, int grid, hipStream_t s) {
+  const dim3 g(grid), blk(kBlock);
+  if (drift)
+    hipLaunchKernelGGL((walk_int01_kernel<N, true>), g, blk, 0, s, a);
+  else
+    hipLaunchKernelGGL((walk_int01_kernel<N, false>), g, blk, 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define PERM_CASE(N) \
+  case N:            \
+    return dispatch<N>(drift, a, grid, s);
+
+hipError_t launch_walk_int01(int n, bool drift, const WalkArgs& a, int grid, hipStream_t s) {
+  switch (n) {
+#include "perm_cases.inc"
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace perm

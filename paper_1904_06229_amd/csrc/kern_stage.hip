@@ -1,0 +1,231 @@
+// Staging and finishing kernels for the single-matrix path.
+//
+// Staging (one workgroup): checks the input, picks power-of-two row scales,
+// and writes the walk's copy of the matrix (+A then -A, column-major, ld = n;
+// for 0/1 input +2A then -2A as doubles).  Row scaling multiplies row i by
+// 2^e_i; per(DA) = prod_i d_i per(A) for a diagonal D, so the factor is
+// undone exactly at the end.  e_i is chosen so the row's 2-norm lies in
+// [2, 4): the row sums w_i = 1/2 sum_j delta_j a_ij are then of order one,
+// which keeps FP32 products of many of them inside FP32's range.
+//
+// Finishing (one workgroup): adds the per-workgroup partial sums of all walk
+// launches in a fixed order (thread t takes partials t, t+256, ...; then the
+// 256 thread sums are added in thread order), so the result is bit-for-bit
+// reproducible (the paper stores partial sums in an array before the final
+// compensated sum instead of reducing them in arbitrary order, Sec. II.B).
+#include "perm_device.hpp"
+#include "perm_internal.hpp"
+
+namespace perm {
+namespace {
+
+__device__ __forceinline__ bool finite(double x) { return isfinite(x); }
+
+__global__ __launch_bounds__(kBlock) void stage_float_kernel(const double* __restrict__ A, int n,
+                                                             int ld, int is_complex,
+                                                             int row_scaling, double* staged,
+                                                             double* rowabs, int32_t* rowexp,
+                                                             int32_t* status) {
+  __shared__ int32_t s_exp[kMaxN];
+  __shared__ int32_t s_bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  const int cw = is_complex ? 2 : 1;  // doubles per entry
+  if (tid < n) {
+    const int i = tid;
+    double mx = 0.0;
+    bool bad = false;
+    for (int j = 0; j < n; ++j) {
+      for (int c = 0; c < cw; ++c) {
+        const double v = A[cw * ((size_t)i + (size_t)j * ld) + c];
+        if (!finite(v)) bad = true;
+        mx = fmax(mx, fabs(v));
+      }
+    }
+    int e = 0;
+    if (!bad && row_scaling && mx > 0.0) {
+      double ss = 0.0;
+      for (int j = 0; j < n; ++j)
+        for (int c = 0; c < cw; ++c) {
+          const double v = A[cw * ((size_t)i + (size_t)j * ld) + c] / mx;
+          ss += v * v;
+        }
+      int k;
+      frexp(mx * sqrt(ss), &k);  // norm in [2^(k-1), 2^k)
+      e = 2 - k;
+      e = e < -1000 ? -1000 : (e > 1000 ? 1000 : e);
+    }
+    s_exp[i] = e;
+    rowexp[i] = e;
+    if (bad) atomicOr(&s_bad, 1);
+  }
+  __syncthreads();
+  const int nn = n * n;
+  for (int idx = tid; idx < nn; idx += kBlock) {
+    const int i = idx % n, j = idx / n;
+    for (int c = 0; c < cw; ++c) {
+      const double v = ldexp(A[cw * ((size_t)i + (size_t)j * ld) + c], s_exp[i]);
+      staged[cw * idx + c] = v;
+      staged[cw * (nn + idx) + c] = -v;
+    }
+  }
+  __syncthreads();
+  if (tid < n) {
+    const int i = tid;
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) {
+      const size_t o = (size_t)cw * (i + (size_t)j * n);
+      s += is_complex ? hypot(staged[o], staged[o + 1]) : fabs(staged[o]);
+    }
+    rowabs[i] = 0.5 * s;
+  }
+  if (tid == 0) status[0] = s_bad ? kStNonFinite : kStOk;
+}
+
+// 0/1 input: entries must be 0 or 1.  Writes +2A/-2A, d_i into rowabs, and
+// checks (n-1) + sum_i log2(d_i!)/d_i < 127 (Bregman: per(A) <=
+// prod_i (d_i!)^(1/d_i)), which keeps 2^(n-1) per(A) inside a signed 128-bit
+// integer.
+__global__ __launch_bounds__(kBlock) void stage_int01_kernel(const uint8_t* __restrict__ A, int n,
+                                                             int ld, int range_check,
+                                                             double* staged, double* rowabs,
+                                                             int32_t* rowexp, int32_t* status,
+                                                             double* bound) {
+  __shared__ int32_t s_bad;
+  __shared__ double s_term[kMaxN];
+  __shared__ int32_t s_zero;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_bad = 0;
+    s_zero = 0;
+  }
+  __syncthreads();
+  const int nn = n * n;
+  for (int idx = tid; idx < nn; idx += kBlock) {
+    const int i = idx % n, j = idx / n;
+    const uint8_t v = A[(size_t)i + (size_t)j * ld];
+    if (v > 1) atomicOr(&s_bad, 1);
+    staged[idx] = 2.0 * v;
+    staged[nn + idx] = -2.0 * v;
+  }
+  if (tid < n) {
+    const int i = tid;
+    int d = 0;
+    for (int j = 0; j < n; ++j) d += A[(size_t)i + (size_t)j * ld] ? 1 : 0;
+    rowabs[i] = (double)d;
+    rowexp[i] = 0;
+    double lf = 0.0;
+    for (int k = 2; k <= d; ++k) lf += log2((double)k);
+    s_term[i] = d > 0 ? lf / d : 0.0;
+    if (d == 0) atomicOr(&s_zero, 1);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double bsum = 0.0;
+    for (int i = 0; i < n; ++i) bsum += s_term[i];
+    const double lb = s_zero ? 0.0 : (double)(n - 1) + bsum;
+    bound[0] = lb;
+    int32_t st = kStOk;
+    if (s_bad)
+      st = kStInval;
+    else if (range_check && lb >= 127.0)
+      st = kStRange;
+    status[0] = st;
+  }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kBlock) void finish_kernel(const void* __restrict__ partials,
+                                                        int nparts,
+                                                        const double* __restrict__ drift_part,
+                                                        int want_drift,
+                                                        const int32_t* __restrict__ status,
+                                                        const int32_t* __restrict__ rowexp, int n,
+                                                        const double* __restrict__ bound,
+                                                        DevResult* res) {
+  const int tid = threadIdx.x;
+  __shared__ dd s_re[kBlock], s_im[kBlock];
+  __shared__ u128 s_i[kBlock];
+  __shared__ double s_dr[kBlock];
+  dd re{0.0, 0.0}, im{0.0, 0.0};
+  u128 iv{0, 0};
+  double dr = 0.0;
+  for (int k = tid; k < nparts; k += kBlock) {
+    if constexpr (KIND == kReal) {
+      const double* p = (const double*)partials;
+      re = dd_add(re, dd{p[2 * k], p[2 * k + 1]});
+    } else if constexpr (KIND == kComplex) {
+      const double* p = (const double*)partials;
+      re = dd_add(re, dd{p[4 * k], p[4 * k + 1]});
+      im = dd_add(im, dd{p[4 * k + 2], p[4 * k + 3]});
+    } else {
+      const uint64_t* p = (const uint64_t*)partials;
+      iv = u128_add(iv, u128{p[2 * k], p[2 * k + 1]});
+    }
+    if (want_drift) dr = fmax(dr, drift_part[k]);
+  }
+  s_re[tid] = re;
+  s_im[tid] = im;
+  s_i[tid] = iv;
+  s_dr[tid] = dr;
+  __syncthreads();
+  if (tid == 0) {
+    for (int t = 1; t < kBlock; ++t) {
+      re = dd_add(re, s_re[t]);
+      im = dd_add(im, s_im[t]);
+      iv = u128_add(iv, s_i[t]);
+      dr = fmax(dr, s_dr[t]);
+    }
+    int32_t es = 0;
+    for (int i = 0; i < n; ++i) es += rowexp[i];
+    res->v[0] = re.hi;
+    res->v[1] = re.lo;
+    res->v[2] = im.hi;
+    res->v[3] = im.lo;
+    res->iw[0] = iv.lo;
+    res->iw[1] = iv.hi;
+    res->drift = want_drift ? dr : -1.0;
+    res->status = status[0];
+    res->exp_sum = es;
+    res->bound = bound ? bound[0] : 0.0;
+    res->pad = 0.0;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_stage(int kind, const void* A, int n, int ld, int row_scaling, int range_check,
+                        double* staged, double* rowabs, int32_t* rowexp, int32_t* status,
+                        double* bound, hipStream_t s) {
+  if (kind == kInt01) {
+    hipLaunchKernelGGL(stage_int01_kernel, dim3(1), dim3(kBlock), 0, s, (const uint8_t*)A, n, ld,
+                       range_check, staged, rowabs, rowexp, status, bound);
+  } else {
+    hipLaunchKernelGGL(stage_float_kernel, dim3(1), dim3(kBlock), 0, s, (const double*)A, n, ld,
+                       kind == kComplex ? 1 : 0, row_scaling, staged, rowabs, rowexp, status);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(int kind, const void* partials, int nparts, const double* drift_part,
+                         int want_drift, const int32_t* status, const int32_t* rowexp, int n,
+                         const double* bound, DevResult* res, hipStream_t s) {
+  switch (kind) {
+    case kReal:
+      hipLaunchKernelGGL(finish_kernel<kReal>, dim3(1), dim3(kBlock), 0, s, partials, nparts,
+                         drift_part, want_drift, status, rowexp, n, bound, res);
+      break;
+    case kComplex:
+      hipLaunchKernelGGL(finish_kernel<kComplex>, dim3(1), dim3(kBlock), 0, s, partials, nparts,
+                         drift_part, want_drift, status, rowexp, n, bound, res);
+      break;
+    default:
+      hipLaunchKernelGGL(finish_kernel<kInt01>, dim3(1), dim3(kBlock), 0, s, partials, nparts,
+                         drift_part, want_drift, status, rowexp, n, bound, res);
+      break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace perm

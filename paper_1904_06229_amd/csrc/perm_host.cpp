@@ -1,0 +1,481 @@
+// C-ABI runtime of the permanent library: argument checks, the chunk plan,
+// per-device workspace, launch sequence and result assembly.
+//
+// Launch sequence of a single-matrix call (all on the caller's stream):
+//   stage (validate, row exponents, +A/-A)  ->  walk: head (single terms),
+//   body (aligned chunks), tail (single terms)  ->  finish (fixed-order sum of
+//   the per-workgroup partials)  ->  copy of one small record to pinned host
+//   memory  ->  wait for the stream  ->  scale by 2(-1)^n and 2^-(row exponents).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "../../include/perm.h"
+#include "perm_batched_host.hpp"
+#include "perm_internal.hpp"
+
+using namespace perm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+perm_status fail(perm_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(PERM_EHIP, std::string(#expr) + " failed: " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kMaxParts = 3 * 65536;
+constexpr int kFloatChunkCap = 24;
+constexpr int kInt01ChunkCap = 10;
+
+struct Workspace {
+  int device = -1;
+  char* dmem = nullptr;
+  DevResult* hres = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  int cu_count = 0;
+  // device sub-buffers
+  int32_t* status = nullptr;
+  int32_t* rowexp = nullptr;
+  double* bound = nullptr;
+  DevResult* dres = nullptr;
+  double* rowabs = nullptr;
+  double* staged = nullptr;
+  void* partials = nullptr;
+  double* drift = nullptr;
+};
+
+std::mutex g_mu;
+std::map<int, Workspace*> g_ws;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+perm_status get_workspace(Workspace** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_ws.find(dev);
+  if (it != g_ws.end()) {
+    *out = it->second;
+    return PERM_OK;
+  }
+  Workspace* w = new Workspace();
+  w->device = dev;
+  size_t off = 0;
+  const size_t o_status = off;
+  off = align_up(off + 64, 256);
+  const size_t o_rowexp = off;
+  off = align_up(off + sizeof(int32_t) * kMaxN, 256);
+  const size_t o_bound = off;
+  off = align_up(off + 64, 256);
+  const size_t o_res = off;
+  off = align_up(off + sizeof(DevResult), 256);
+  const size_t o_rowabs = off;
+  off = align_up(off + sizeof(double) * kMaxN, 256);
+  const size_t o_staged = off;
+  off = align_up(off + sizeof(double) * 4 * kMaxN * kMaxN, 256);
+  const size_t o_part = off;
+  off = align_up(off + sizeof(double) * 4 * (size_t)kMaxParts, 256);
+  const size_t o_drift = off;
+  off = align_up(off + sizeof(double) * (size_t)kMaxParts, 256);
+  hipError_t e = hipMalloc((void**)&w->dmem, off);
+  if (e != hipSuccess) {
+    delete w;
+    return fail(PERM_ENOMEM, std::string("hipMalloc of workspace failed: ") + hipGetErrorString(e));
+  }
+  e = hipHostMalloc((void**)&w->hres, sizeof(DevResult), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    (void)hipFree(w->dmem);
+    delete w;
+    return fail(PERM_ENOMEM, std::string("hipHostMalloc failed: ") + hipGetErrorString(e));
+  }
+  for (auto& ev : w->ev) {
+    e = hipEventCreate(&ev);
+    if (e != hipSuccess) return fail(PERM_EHIP, std::string("hipEventCreate failed: ") + hipGetErrorString(e));
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    w->cu_count = prop.multiProcessorCount;
+  if (w->cu_count <= 0) w->cu_count = 256;
+  w->status = (int32_t*)(w->dmem + o_status);
+  w->rowexp = (int32_t*)(w->dmem + o_rowexp);
+  w->bound = (double*)(w->dmem + o_bound);
+  w->dres = (DevResult*)(w->dmem + o_res);
+  w->rowabs = (double*)(w->dmem + o_rowabs);
+  w->staged = (double*)(w->dmem + o_staged);
+  w->partials = (void*)(w->dmem + o_part);
+  w->drift = (double*)(w->dmem + o_drift);
+  g_ws[dev] = w;
+  *out = w;
+  return PERM_OK;
+}
+
+uint64_t total_terms(int n) { return n >= 64 ? (1ull << 63) : (1ull << (n - 1)); }
+
+int floor_log2(uint64_t x) { return x ? 63 - __builtin_clzll(x) : -1; }
+
+// Automatic chunk length: enough chunks to give every SIMD several waves
+// (2^18 lane chunks), chunks no longer than the cap.
+int auto_log2_chunk(uint64_t count, int cap) {
+  int b = floor_log2(count) - 18;
+  if (b < 0) b = 0;
+  if (b > cap) b = cap;
+  return b;
+}
+
+int grid_for(uint64_t tasks, int cap_blocks) {
+  uint64_t blocks = (tasks + kWavesPerBlock - 1) / kWavesPerBlock;
+  if (blocks > (uint64_t)cap_blocks) blocks = (uint64_t)cap_blocks;
+  if (blocks < 1) blocks = 1;
+  return (int)blocks;
+}
+
+perm_status check_opts(const perm_opts* o, int is_int01) {
+  if (!o) return PERM_OK;
+  if (o->precision < 0 || o->precision > 2) return fail(PERM_EINVAL, "precision must be 0, 1 or 2");
+  const int cap = is_int01 ? kInt01ChunkCap : kFloatChunkCap;
+  if (o->log2_chunk < 0 || o->log2_chunk > cap)
+    return fail(PERM_EINVAL, "log2_chunk out of range (max " + std::to_string(cap) + ")");
+  if (o->blocks < 0 || o->blocks > kMaxParts / 3) return fail(PERM_EINVAL, "blocks out of range");
+  if (o->drift_check < 0 || o->drift_check > 1) return fail(PERM_EINVAL, "drift_check must be 0 or 1");
+  if (o->reserved[0] || o->reserved[1]) return fail(PERM_EINVAL, "reserved options must be 0");
+  return PERM_OK;
+}
+
+int to_int(perm_status s) { return (int)s; }
+
+struct Raw {
+  DevResult r;
+  perm_plan_info plan;
+  float kernel_ms, total_ms;
+  int blocks;
+};
+
+perm_status launch_walk(int kind, int n, int mode, bool drift, const WalkArgs& a, int grid,
+                        hipStream_t s) {
+  hipError_t e;
+  if (kind == kReal)
+    e = launch_walk_real(n, mode, drift, a, grid, s);
+  else if (kind == kComplex)
+    e = launch_walk_complex(n, mode, drift, a, grid, s);
+  else
+    e = launch_walk_int01(n, drift, a, grid, s);
+  if (e != hipSuccess) return fail(PERM_EHIP, std::string("walk launch failed: ") + hipGetErrorString(e));
+  return PERM_OK;
+}
+
+// Stage, walk [start, start+count), finish, and bring the record back.
+perm_status run_range(int kind, const void* dA, int n, int ld, uint64_t start, uint64_t count,
+                      const perm_opts* opts, int range_check, hipStream_t s, Raw* raw) {
+  perm_opts o{};
+  if (opts) o = *opts;
+  const int is_int = kind == kInt01;
+  perm_plan_info plan;
+  perm_status st = perm_plan(n, start, count, o.log2_chunk, is_int, &plan);
+  if (st != PERM_OK) return st;
+  Workspace* ws = nullptr;
+  st = get_workspace(&ws);
+  if (st != PERM_OK) return st;
+  const int cap = o.blocks > 0 ? o.blocks : 4 * ws->cu_count;
+  const bool drift = o.drift_check != 0;
+  const int mode = is_int ? 0 : o.precision;
+
+  HIP_TRY(hipEventRecord(ws->ev[0], s));
+  HIP_TRY(launch_stage(kind, dA, n, ld, o.no_row_scaling ? 0 : 1, range_check, ws->staged,
+                       ws->rowabs, ws->rowexp, ws->status, ws->bound, s));
+
+  int nparts = 0;
+  int body_grid = 0;
+  char* part_base = (char*)ws->partials;
+  const size_t part_bytes = (kind == kComplex) ? 32 : 16;
+  auto walk = [&](uint64_t first, uint64_t nchunks, int b, int* grid_out) -> perm_status {
+    if (nchunks == 0) return PERM_OK;
+    WalkArgs a;
+    a.staged = ws->staged;
+    a.rowabs = ws->rowabs;
+    a.status = ws->status;
+    a.first = first;
+    a.nchunks = nchunks;
+    a.ntasks = 2 * ((nchunks + 2 * kWave - 1) / (2 * kWave));
+    a.b = b;
+    a.drift = drift ? 1 : 0;
+    a.partials = part_base + part_bytes * nparts;
+    a.drift_part = ws->drift + nparts;
+    const int grid = grid_for(a.ntasks, cap);
+    if (grid_out) *grid_out = grid;
+    nparts += grid;
+    return launch_walk(kind, n, mode, drift, a, grid, s);
+  };
+
+  HIP_TRY(hipEventRecord(ws->ev[1], s));
+  if ((st = walk(plan.head_start, plan.head_count, 0, nullptr)) != PERM_OK) return st;
+  if ((st = walk(plan.body_first_chunk, plan.body_chunks, plan.log2_chunk, &body_grid)) != PERM_OK)
+    return st;
+  if ((st = walk(plan.tail_start, plan.tail_count, 0, nullptr)) != PERM_OK) return st;
+  HIP_TRY(hipEventRecord(ws->ev[2], s));
+  HIP_TRY(launch_finish(kind, ws->partials, nparts, ws->drift, drift ? 1 : 0, ws->status,
+                        ws->rowexp, n, ws->bound, ws->dres, s));
+  HIP_TRY(hipMemcpyAsync(ws->hres, ws->dres, sizeof(DevResult), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipEventRecord(ws->ev[3], s));
+  HIP_TRY(hipStreamSynchronize(s));
+  raw->r = *ws->hres;
+  raw->plan = plan;
+  raw->blocks = body_grid;
+  raw->kernel_ms = raw->total_ms = 0.0f;
+  (void)hipEventElapsedTime(&raw->kernel_ms, ws->ev[1], ws->ev[2]);
+  (void)hipEventElapsedTime(&raw->total_ms, ws->ev[0], ws->ev[3]);
+  return PERM_OK;
+}
+
+void fill_common(const Raw& raw, uint64_t count, perm_result* out) {
+  out->max_drift = raw.r.drift;
+  out->terms = count;
+  out->chunks = raw.plan.body_chunks + raw.plan.head_count + raw.plan.tail_count;
+  out->log2_chunk = raw.plan.log2_chunk;
+  out->blocks = raw.blocks;
+  out->kernel_ms = raw.kernel_ms;
+  out->total_ms = raw.total_ms;
+}
+
+perm_status status_from_device(int32_t st) {
+  switch (st) {
+    case kStOk: return PERM_OK;
+    case kStNonFinite: return fail(PERM_ENONFINITE, "matrix has a NaN or infinite entry");
+    case kStInval: return fail(PERM_EINVAL, "0/1 matrix has an entry other than 0 or 1");
+    case kStRange:
+      return fail(PERM_ERANGE, "exact 0/1 result may exceed 128 bits (Bregman bound >= 127)");
+    default: return fail(PERM_EHIP, "unexpected device status");
+  }
+}
+
+void pair_from_i128(__int128 v, double* hi, double* lo) {
+  const double h = (double)v;
+  *hi = h;
+  if (std::fabs(h) >= 1.7014118346046923e38) {  // 2^127: no exact difference in 128 bits
+    *lo = 0.0;
+    return;
+  }
+  *lo = (double)(v - (__int128)h);
+}
+
+perm_status float_call(int kind, const double* dA, int n, int ld, const perm_opts* opts,
+                       perm_result* out, void* stream) {
+  if (!out) return fail(PERM_EINVAL, "out is NULL");
+  if (n < 0 || n > kMaxN) return fail(PERM_EINVAL, "n must be in [0, 64]");
+  if (ld < std::max(n, 1)) return fail(PERM_EINVAL, "ld must be >= n");
+  perm_status st = check_opts(opts, 0);
+  if (st != PERM_OK) return st;
+  if (n == 0) {
+    perm_result r{};
+    r.re_hi = 1.0;
+    r.max_drift = -1.0;
+    *out = r;
+    return PERM_OK;
+  }
+  if (!dA) return fail(PERM_EINVAL, "dA is NULL");
+  const uint64_t T = total_terms(n);
+  Raw raw;
+  st = run_range(kind, dA, n, ld, 0, T, opts, 0, (hipStream_t)stream, &raw);
+  if (st != PERM_OK) return st;
+  st = status_from_device(raw.r.status);
+  if (st != PERM_OK) return st;
+  // per = 2 (-1)^n S, then undo the row scaling 2^(sum e_i).
+  const double f = (n % 2 == 0) ? 2.0 : -2.0;
+  const int e = -raw.r.exp_sum;
+  perm_result r{};
+  r.re_hi = std::ldexp(f * raw.r.v[0], e);
+  r.re_lo = std::ldexp(f * raw.r.v[1], e);
+  r.im_hi = std::ldexp(f * raw.r.v[2], e);
+  r.im_lo = std::ldexp(f * raw.r.v[3], e);
+  fill_common(raw, T, &r);
+  *out = r;
+  return PERM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+perm_status perm_plan(int n, uint64_t start, uint64_t count, int log2_chunk, int is_int01,
+                      perm_plan_info* out) {
+  if (!out) return fail(PERM_EINVAL, "out is NULL");
+  if (n < 1 || n > kMaxN) return fail(PERM_EINVAL, "n must be in [1, 64]");
+  const uint64_t T = total_terms(n);
+  if (start > T || count > T - start) return fail(PERM_EINVAL, "range outside [0, 2^(n-1))");
+  const int cap = is_int01 ? kInt01ChunkCap : kFloatChunkCap;
+  if (log2_chunk < 0 || log2_chunk > cap) return fail(PERM_EINVAL, "log2_chunk out of range");
+  int b = log2_chunk > 0 ? log2_chunk : auto_log2_chunk(count, is_int01 ? kInt01ChunkCap : 12);
+  const uint64_t L = 1ull << b;
+  const uint64_t end = start + count;
+  uint64_t a0 = (start + L - 1) / L * L;
+  if (a0 > end || a0 < start) a0 = end;
+  const uint64_t a1 = a0 + (end - a0) / L * L;
+  perm_plan_info p{};
+  p.log2_chunk = b;
+  p.head_start = start;
+  p.head_count = a0 - start;
+  p.body_first_chunk = a0 / L;
+  p.body_chunks = (a1 - a0) / L;
+  p.tail_start = a1;
+  p.tail_count = end - a1;
+  p.body_tasks = 2 * ((p.body_chunks + 2 * kWave - 1) / (2 * kWave));
+  *out = p;
+  return PERM_OK;
+}
+
+double perm_int01_bound(const int32_t* d, int n) {
+  if (n <= 0) return 0.0;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) {
+    if (d[i] <= 0) return 0.0;
+    double lf = 0.0;
+    for (int k = 2; k <= d[i]; ++k) lf += std::log2((double)k);
+    s += lf / d[i];
+  }
+  return (double)(n - 1) + s;
+}
+
+perm_status perm_real(const double* dA, int n, int ld, const perm_opts* opts, perm_result* out,
+                      void* stream) {
+  return float_call(kReal, dA, n, ld, opts, out, stream);
+}
+
+perm_status perm_complex(const double* dA, int n, int ld, const perm_opts* opts,
+                         perm_result* out, void* stream) {
+  return float_call(kComplex, dA, n, ld, opts, out, stream);
+}
+
+perm_status perm_int01(const uint8_t* dA, int n, int ld, const perm_opts* opts, perm_result* out,
+                       void* stream) {
+  if (!out) return fail(PERM_EINVAL, "out is NULL");
+  if (n < 0 || n > kMaxN) return fail(PERM_EINVAL, "n must be in [0, 64]");
+  if (ld < std::max(n, 1)) return fail(PERM_EINVAL, "ld must be >= n");
+  perm_status st = check_opts(opts, 1);
+  if (st != PERM_OK) return st;
+  if (n == 0) {
+    perm_result r{};
+    r.re_hi = 1.0;
+    r.int_lo = 1;
+    r.max_drift = -1.0;
+    *out = r;
+    return PERM_OK;
+  }
+  if (!dA) return fail(PERM_EINVAL, "dA is NULL");
+  const uint64_t T = total_terms(n);
+  Raw raw;
+  st = run_range(kInt01, dA, n, ld, 0, T, opts, 1, (hipStream_t)stream, &raw);
+  if (st != PERM_OK) return st;
+  st = status_from_device(raw.r.status);
+  if (st != PERM_OK) return st;
+  // S = (-1)^n 2^(n-1) per(A) modulo 2^128, with |S| < 2^127 by the guard.
+  const unsigned __int128 u = ((unsigned __int128)raw.r.iw[1] << 64) | raw.r.iw[0];
+  const __int128 S = (__int128)u;
+  const unsigned __int128 low_mask = (((unsigned __int128)1) << (n - 1)) - 1;
+  if ((u & low_mask) != 0)
+    return fail(PERM_EHIP, "internal check failed: 0/1 sum not divisible by 2^(n-1)");
+  __int128 per = S >> (n - 1);  // exact division (low bits are zero)
+  if (n % 2) per = -per;
+  perm_result r{};
+  r.int_lo = (uint64_t)(unsigned __int128)per;
+  r.int_hi = (int64_t)(per >> 64);
+  pair_from_i128(per, &r.re_hi, &r.re_lo);
+  fill_common(raw, T, &r);
+  *out = r;
+  return PERM_OK;
+}
+
+perm_status perm_partial(int dtype, const void* dA, int n, int ld, uint64_t start, uint64_t count,
+                         const perm_opts* opts, perm_result* out, void* stream) {
+  if (!out) return fail(PERM_EINVAL, "out is NULL");
+  if (dtype < 0 || dtype > 2) return fail(PERM_EINVAL, "dtype must be 0, 1 or 2");
+  if (n < 1 || n > kMaxN) return fail(PERM_EINVAL, "n must be in [1, 64]");
+  if (ld < n) return fail(PERM_EINVAL, "ld must be >= n");
+  if (!dA) return fail(PERM_EINVAL, "dA is NULL");
+  const int kind = dtype == PERM_DT_REAL ? kReal : (dtype == PERM_DT_COMPLEX ? kComplex : kInt01);
+  perm_status st = check_opts(opts, kind == kInt01);
+  if (st != PERM_OK) return st;
+  const uint64_t T = total_terms(n);
+  if (start > T || count > T - start) return fail(PERM_EINVAL, "range outside [0, 2^(n-1))");
+  perm_result r{};
+  r.max_drift = -1.0;
+  if (count == 0) {
+    *out = r;
+    return PERM_OK;
+  }
+  Raw raw;
+  st = run_range(kind, dA, n, ld, start, count, opts, 0, (hipStream_t)stream, &raw);
+  if (st != PERM_OK) return st;
+  st = status_from_device(raw.r.status);
+  if (st != PERM_OK) return st;
+  if (kind == kInt01) {
+    r.int_lo = raw.r.iw[0];
+    r.int_hi = (int64_t)raw.r.iw[1];
+    const __int128 v = (__int128)(((unsigned __int128)raw.r.iw[1] << 64) | raw.r.iw[0]);
+    pair_from_i128(v, &r.re_hi, &r.re_lo);
+  } else {
+    const int e = -raw.r.exp_sum;
+    r.re_hi = std::ldexp(raw.r.v[0], e);
+    r.re_lo = std::ldexp(raw.r.v[1], e);
+    r.im_hi = std::ldexp(raw.r.v[2], e);
+    r.im_lo = std::ldexp(raw.r.v[3], e);
+  }
+  fill_common(raw, count, &r);
+  *out = r;
+  return PERM_OK;
+}
+
+const char* perm_strerror(perm_status s) {
+  switch (s) {
+    case PERM_OK: return "success";
+    case PERM_EINVAL: return "invalid argument";
+    case PERM_ERANGE: return "exact result out of the 128-bit range";
+    case PERM_ENONFINITE: return "non-finite matrix entry";
+    case PERM_ENOMEM: return "out of memory";
+    case PERM_EHIP: return "HIP runtime error";
+    case PERM_ENOTIMPL: return "not implemented";
+  }
+  return "unknown status";
+}
+
+const char* perm_last_error(void) { return g_last_error.c_str(); }
+
+const char* perm_version(void) { return "perm-mi355x 0.1 (gfx950)"; }
+
+void perm_release(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (auto& kv : g_ws) {
+    Workspace* w = kv.second;
+    (void)hipSetDevice(w->device);
+    (void)hipDeviceSynchronize();
+    for (auto& ev : w->ev)
+      if (ev) (void)hipEventDestroy(ev);
+    if (w->hres) (void)hipHostFree(w->hres);
+    if (w->dmem) (void)hipFree(w->dmem);
+    delete w;
+  }
+  g_ws.clear();
+  perm::batched_release();
+  (void)hipSetDevice(cur);
+}
+
+}  // extern "C"
+
+namespace perm {
+perm_status set_error(perm_status s, const char* msg) { return fail(s, msg); }
+}  // namespace perm

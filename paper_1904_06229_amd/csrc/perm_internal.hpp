@@ -1,0 +1,115 @@
+// Host-side interface between the C-ABI runtime (perm_host.cpp) and the
+// kernel sources.  Plain structs and launch functions; no torch types.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace perm {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;  // 4 waves per workgroup, one per SIMD
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+constexpr int kMaxN = 64;
+constexpr int kMaxBatchedN = 32;
+
+// Status codes written by the staging kernels (same values as perm_status).
+constexpr int32_t kStOk = 0;
+constexpr int32_t kStInval = 1;
+constexpr int32_t kStRange = 2;
+constexpr int32_t kStNonFinite = 3;
+
+// One walk launch: chunks [first, first + nchunks) of length 2^b, i.e.
+// Gray indices [first * 2^b, (first + nchunks) * 2^b).  b = 0 walks single
+// terms (used for unaligned range ends).
+struct WalkArgs {
+  const double* staged;   // +A then -A, column-major, ld = n (complex: pairs)
+  const double* rowabs;   // n values 1/2 sum_j |a_ij| (drift normalisation)
+  const int32_t* status;  // staging status; nonzero -> the walk does nothing
+  uint64_t first;
+  uint64_t nchunks;
+  uint64_t ntasks;        // wave tasks: 2 * ceil(nchunks / 128)
+  int32_t b;
+  int32_t drift;          // 1: compute the chunk-end drift
+  void* partials;         // per workgroup: dd (2 doubles), complex dd (4), or u128 (2 words)
+  double* drift_part;     // per workgroup
+};
+
+// Result record written by the finishing kernel, copied to the host.
+struct DevResult {
+  double v[4];        // re hi, re lo, im hi, im lo (raw sum S, before 2(-1)^n and unscaling)
+  uint64_t iw[2];     // 0/1 path: sum_g (-1)^(g+1) prod r_i modulo 2^128
+  double drift;       // max drift (or -1)
+  int32_t status;
+  int32_t exp_sum;    // sum of row-scaling exponents
+  double bound;       // 0/1 path: log2 accumulator bound
+  double pad;
+};
+
+enum Kind { kReal = 0, kComplex = 1, kInt01 = 2 };
+
+hipError_t launch_walk_real(int n, int mode, bool drift, const WalkArgs& a, int grid,
+                            hipStream_t s);
+hipError_t launch_walk_complex(int n, int mode, bool drift, const WalkArgs& a, int grid,
+                               hipStream_t s);
+hipError_t launch_walk_int01(int n, bool drift, const WalkArgs& a, int grid, hipStream_t s);
+
+// Staging: validate A, choose row exponents, write +A/-A (0/1: +2A/-2A).
+hipError_t launch_stage(int kind, const void* A, int n, int ld, int row_scaling, int range_check,
+                        double* staged, double* rowabs, int32_t* rowexp, int32_t* status,
+                        double* bound, hipStream_t s);
+
+// Fixed-order sum of the per-workgroup partials into a DevResult.
+hipError_t launch_finish(int kind, const void* partials, int nparts, const double* drift_part,
+                         int want_drift, const int32_t* status, const int32_t* rowexp, int n,
+                         const double* bound, DevResult* res, hipStream_t s);
+
+// ---------------------------------------------------------------- batched ----
+
+// One queue item: 64 lane chunks of one matrix (wave task `task` of its body).
+struct BatchItem {
+  int32_t mat;     // matrix index
+  int32_t n;
+  int32_t b;       // log2 chunk length
+  int32_t pad;
+  uint64_t task;   // wave task within the matrix (see task_chunk)
+  uint64_t nchunks;
+};
+
+struct BatchArgs {
+  const double* staged;      // staged matrices (per matrix: +A then -A)
+  const int64_t* st_off;     // offset of matrix m's staged block (doubles)
+  const int32_t* mstatus;    // per-matrix staging status
+  const BatchItem* items;
+  uint64_t nitems;
+  unsigned int* counter;     // queue head; reset to 0 before every launch
+  double* slots;             // 4 doubles per item
+};
+
+hipError_t launch_batched_stage(int is_complex, const double* A, const int64_t* d_off,
+                                const int32_t* d_n, int count, int row_scaling, double* staged,
+                                const int64_t* st_off, int32_t* rowexp_sum, int32_t* mstatus,
+                                hipStream_t s);
+hipError_t launch_batched_walk(int is_complex, int max_n, const BatchArgs& a, int grid,
+                               hipStream_t s);
+hipError_t launch_batched_reset(unsigned int* counter, hipStream_t s);
+hipError_t launch_batched_finish(int is_complex, const double* slots, const int64_t* item_first,
+                                 const int32_t* item_count, const int32_t* d_n,
+                                 const int32_t* rowexp_sum, const int32_t* mstatus, int count,
+                                 double* d_out, int32_t* d_status, hipStream_t s);
+
+// Rows per exactly-multiplied group in the 0/1 walk: the largest k with
+// n^k < 2^50 (|2 w_i| <= n, so a group's product stays below 2^50).
+constexpr int int01_group_rows(int n) {
+  if (n <= 1) return 1;
+  int k = 0;
+  double p = 1.0;
+  while (p * n < 1125899906842624.0) {
+    p *= n;
+    ++k;
+  }
+  return k;
+}
+
+}  // namespace perm
