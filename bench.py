@@ -47,7 +47,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c5"])
+    p.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    p.add_argument("--count", type=int, default=100000, help="c4: number of matrices")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--blocks", type=int, default=0)
     p.add_argument("--log2-chunk", type=int, default=0)
@@ -101,11 +102,115 @@ def cpu_baseline(kind, n, A):
             "sample": sample, "seconds": round(dt, 3)}
 
 
+def gpu_qr(G):
+    """Stacked reduced QR on the GPU (input generation only)."""
+    import torch
+    Q, R = torch.linalg.qr(torch.from_numpy(G).to("cuda"), mode="reduced")
+    return Q.cpu().numpy(), R.cpu().numpy()
+
+
+def exact_mean_x2(n, m):
+    """E[m^n |per U_n|^2 / n!] for the n x n block of an m-mode Haar unitary:
+    prod_{k<n} m/(m+k) (a soft statistical check, not from the paper)."""
+    return math.prod(m / (m + k) for k in range(n))
+
+
+def bench_batched(args):
+    import numpy as np
+    import torch
+    from paper_1904_06229_amd import binding as B, inputs
+
+    seed = 20190404
+    t0 = time.perf_counter()
+    sizes, mats = inputs.batched_haar_blocks(args.count, 8, 24, seed, qr=gpu_qr)
+    gen_s = time.perf_counter() - t0
+    parts, offs, o = [], [], 0
+    for M in mats:
+        flat = np.asfortranarray(M).ravel(order="F").view(np.float64)
+        parts.append(flat)
+        offs.append(o)
+        o += flat.size
+    dA = torch.from_numpy(np.concatenate(parts)).to("cuda")
+    count = len(sizes)
+    out = torch.zeros(4 * count, dtype=torch.float64, device="cuda")
+    st = torch.zeros(count, dtype=torch.int32, device="cuda")
+    t1 = time.perf_counter()
+    B.perm_autotune(True, 8, 24)
+    tune_s = time.perf_counter() - t1
+    s = torch.cuda.Stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(s):
+        for _ in range(args.warmup):
+            B.perm_batched(dA, sizes, offs, True, out, st, stream=s, use_graph=True)
+        s.synchronize()
+        kms = []
+        t2 = time.perf_counter()
+        for _ in range(args.steps):
+            ev0.record(s)
+            B.perm_batched(dA, sizes, offs, True, out, st, stream=s, use_graph=True)
+            ev1.record(s)
+            ev1.synchronize()
+            kms.append(ev0.elapsed_time(ev1))
+        dt = time.perf_counter() - t2
+    res = out.cpu().numpy().reshape(-1, 4)
+    per = res[:, 0] + res[:, 1] + 1j * (res[:, 2] + res[:, 3])
+    assert (st.cpu().numpy() == 0).all()
+    steps_elem = sum(n * 2.0 ** (n - 1) for n in sizes)
+    ops = sum(algorithmic_ops_per_term("complex", n) * 2.0 ** (n - 1) for n in sizes)
+    kavg = sum(kms) / len(kms)
+    # X^2 = m^n |per U_n|^2 / n!, m = n^2 (the paper's normalisation of S(m, n), Sec. VI)
+    sz = np.array(sizes)
+    x2 = np.array([(n * n) ** n * abs(p) ** 2 / math.factorial(n) for n, p in zip(sizes, per)])
+    mean_check = {str(n): [float(x2[sz == n].mean()), exact_mean_x2(n, n * n)]
+                  for n in (8, 16, 24)}
+    edges = 10.0 ** (np.arange(-6 * 16, 2 * 16 + 1) / 16.0)  # 16 points per decade
+    hist = np.histogram(np.sqrt(x2), bins=edges)[0]
+    outj = {
+        "metric": "batched permanents/s",
+        "value": args.steps * count / dt,
+        "unit": "permanents/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{count} complex Haar blocks U_n of n^2-mode unitaries, "
+                               f"n uniform on 8..24, seed {seed}",
+                   "element_steps_per_s": args.steps * steps_elem / dt,
+                   "generate_s": round(gen_s, 2), "autotune_s": round(tune_s, 2)},
+        "roofline": {"bound": "alu", "achieved": ops / (kavg * 1e-3) / 1e12,
+                     "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
+                     "frac": ops / (kavg * 1e-3) / PEAK_LANE_OPS, "traffic": None,
+                     "kernel": "batched stage+walk+finish (graph)", "kernel_ms": kavg},
+        "mean_X2_vs_exact": mean_check,
+        "histogram_sqrtX2_16_per_decade_nonzero": int((hist > 0).sum()),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        rng = np.random.default_rng(seed + 1)
+        pick = rng.choice(count, size=max(1, count // 100), replace=False)
+        t3 = time.perf_counter()
+        worst = 0.0
+        for k in pick:
+            w = oracle.ryser(mats[k])
+            want = complex(w.re.hi + w.re.lo, w.im.hi + w.im.lo)
+            worst = max(worst, abs(per[k] - want) / abs(want))
+        odt = time.perf_counter() - t3
+        outj["subsample_max_rel_err"] = worst
+        outj["cpu_baseline"] = {"value": len(pick) / odt, "unit": "permanents/s",
+                                "cores": oracle.default_threads(), "kind": "oracle",
+                                "sample": f"{len(pick)} seeded matrices (1%) of the batch, "
+                                          "long-double Ryser", "seconds": round(odt, 2)}
+    print(json.dumps(outj))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "c4":
+        return bench_batched(args)
     import numpy as np
     import torch
     from paper_1904_06229_amd import binding as B

@@ -164,28 +164,37 @@ __device__ __forceinline__ void add_col(double (&w)[N], const double* __restrict
   for (int i = 0; i < N; ++i) w[i] += col[i];
 }
 
-// Integer-form sum of chunk G's terms, modulo 2^128.
+// Integer form of the single term g, (-1)^(g+1) prod_i r_i, modulo 2^128.
+// Kept apart from the chunk walk (see single_term_real).
+template <int N>
+__device__ __forceinline__ u128 single_term(const double* __restrict__ staged, uint64_t g) {
+  staged = opaque(staged);
+  double r[N];
+  form_w_real<N>(staged, g, r);
+  Bins B{0, 0, 0};
+  const Bins off = term_offsets<N>();
+  if (g & 1) {
+    term_bins<N, true>(r, B);
+    B.b0 -= off.b0;
+    B.b1 -= off.b1;
+    B.b2 -= off.b2;
+  } else {
+    term_bins<N, false>(r, B);
+    B.b0 += off.b0;
+    B.b1 += off.b1;
+    B.b2 += off.b2;
+  }
+  return fold(B);
+}
+
+// Integer-form sum of chunk G's terms (b >= 1), modulo 2^128.
 template <int N, bool DRIFT>
 __device__ __forceinline__ u128 walk_chunk(const double* __restrict__ staged, uint64_t G, int b,
                                            uint32_t gpar, double& drift) {
+  staged = opaque(staged);
   double r[N];
   form_w_real<N>(staged, G << b, r);  // staged holds +2A/-2A, so this is r = 2w
   Bins B{0, 0, 0};
-  if (b == 0) {
-    const Bins off = term_offsets<N>();
-    if (G & 1) {
-      term_bins<N, true>(r, B);
-      B.b0 -= off.b0;
-      B.b1 -= off.b1;
-      B.b2 -= off.b2;
-    } else {
-      term_bins<N, false>(r, B);
-      B.b0 += off.b0;
-      B.b1 += off.b1;
-      B.b2 += off.b2;
-    }
-    return fold(B);
-  }
   const uint32_t half = 1u << (b - 1);
   uint32_t t = 0;
   for (; t + 1 < half; ++t) {
@@ -209,7 +218,7 @@ __device__ __forceinline__ u128 walk_chunk(const double* __restrict__ staged, ui
   return fold(B);
 }
 
-template <int N, bool DRIFT>
+template <int N, bool DRIFT, bool SINGLE>
 __global__ __launch_bounds__(kBlock) void walk_int01_kernel(WalkArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint64_t wave = wave_id();
@@ -221,7 +230,11 @@ __global__ __launch_bounds__(kBlock) void walk_int01_kernel(WalkArgs a) {
       const uint64_t c = task_chunk(task, lane);
       const uint32_t gpar = (uint32_t)((a.first + (task & 1)) & 1);
       double dr = 0.0;
-      const u128 part = walk_chunk<N, DRIFT>(a.staged, a.first + c, a.b, gpar, dr);
+      u128 part;
+      if constexpr (SINGLE)
+        part = single_term<N>(a.staged, a.first + c);
+      else
+        part = walk_chunk<N, DRIFT>(a.staged, a.first + c, a.b, gpar, dr);
       if (c < a.nchunks) {
         acc = u128_add(acc, part);
         drift = fmax(drift, dr);
@@ -245,10 +258,12 @@ __global__ __launch_bounds__(kBlock) void walk_int01_kernel(WalkArgs a) {
 template <int N>
 hipError_t dispatch(bool drift, const WalkArgs& a, int grid, hipStream_t s) {
   const dim3 g(grid), blk(kBlock);
-  if (drift)
-    hipLaunchKernelGGL((walk_int01_kernel<N, true>), g, blk, 0, s, a);
+  if (a.b == 0)
+    hipLaunchKernelGGL((walk_int01_kernel<N, false, true>), g, blk, 0, s, a);
+  else if (drift)
+    hipLaunchKernelGGL((walk_int01_kernel<N, true, false>), g, blk, 0, s, a);
   else
-    hipLaunchKernelGGL((walk_int01_kernel<N, false>), g, blk, 0, s, a);
+    hipLaunchKernelGGL((walk_int01_kernel<N, false, false>), g, blk, 0, s, a);
   return hipGetLastError();
 }
 

@@ -12,81 +12,12 @@
 // MODE 0: FP64 products, double-double lane sum (default)
 // MODE 1: FP64 products, plain FP64 lane sum
 // MODE 2: FP32 products of the FP64 row sums, double-double lane sum
-#include "perm_device.hpp"
-#include "perm_internal.hpp"
+#include "perm_walk.hpp"
 
 namespace perm {
 namespace {
 
-template <int N, int MODE>
-__device__ __forceinline__ double term_prod(const double (&w)[N]) {
-  if constexpr (MODE == 2)
-    return prod_f32<N>(w);
-  else
-    return prod_f64<N>(w);
-}
-
-template <int N>
-__device__ __forceinline__ void add_col(double (&w)[N], const double* __restrict__ staged,
-                                        uint32_t sub, int j) {
-  cdptr col = as_const(staged + sub * (N * N) + j * N);
-#pragma unroll
-  for (int i = 0; i < N; ++i) w[i] += col[i];
-}
-
-template <int MODE>
-__device__ __forceinline__ void lane_acc(dd& acc, double q) {
-  if constexpr (MODE == 1)
-    acc.hi += q;
-  else
-    dd_acc(acc, q);
-}
-
-// Signed sum of the terms of chunk G (Gray indices [G*L, (G+1)*L)).
-template <int N, int MODE, bool DRIFT>
-__device__ __forceinline__ dd walk_chunk(const double* __restrict__ staged,
-                                         const double* __restrict__ rowabs, uint64_t G, int b,
-                                         uint32_t gpar, double& drift) {
-  double w[N];
-  form_w_real<N>(staged, G << b, w);
-  dd acc{0.0, 0.0};
-  if (b == 0) {
-    const double p = term_prod<N, MODE>(w);
-    acc.hi = (G & 1) ? p : -p;
-    return acc;
-  }
-  const uint32_t half = 1u << (b - 1);
-  uint32_t t = 0;
-  // All pairs but the last: both flips (column 0, then column ctz(2t+2)).
-  for (; t + 1 < half; ++t) {
-    const double p0 = term_prod<N, MODE>(w);
-    add_col<N>(w, staged, t & 1u, 0);
-    const double p1 = term_prod<N, MODE>(w);
-    const uint32_t s1 = 2 * t + 2;
-    const int j = __builtin_ctz(s1);
-    add_col<N>(w, staged, flip_subtracts(s1, j, b, gpar), j);
-    lane_acc<MODE>(acc, p1 - p0);
-  }
-  // Last pair: no flip after the chunk's last term.
-  {
-    const double p0 = term_prod<N, MODE>(w);
-    add_col<N>(w, staged, (b >= 2) ? (t & 1u) : gpar, 0);
-    const double p1 = term_prod<N, MODE>(w);
-    lane_acc<MODE>(acc, p1 - p0);
-  }
-  if constexpr (DRIFT) {
-    double f[N];
-    form_w_real<N>(staged, ((G + 1) << b) - 1, f);
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      const double s = rowabs[i];
-      if (s > 0.0) drift = fmax(drift, fabs(w[i] - f[i]) / s);
-    }
-  }
-  return acc;
-}
-
-template <int N, int MODE, bool DRIFT>
+template <int N, int MODE, bool DRIFT, bool SINGLE>
 __global__ __launch_bounds__(kBlock) void walk_real_kernel(WalkArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint64_t wave = wave_id();
@@ -98,8 +29,11 @@ __global__ __launch_bounds__(kBlock) void walk_real_kernel(WalkArgs a) {
       const uint64_t c = task_chunk(task, lane);
       const uint32_t gpar = (uint32_t)((a.first + (task & 1)) & 1);
       double dr = 0.0;
-      const dd part =
-          walk_chunk<N, MODE, DRIFT>(a.staged, a.rowabs, a.first + c, a.b, gpar, dr);
+      dd part;
+      if constexpr (SINGLE)
+        part = single_term_real<N, MODE>(a.staged, a.first + c);
+      else
+        part = walk_chunk_real<N, MODE, DRIFT>(a.staged, a.rowabs, a.first + c, a.b, gpar, dr);
       if (c < a.nchunks) {
         acc = dd_add(acc, part);
         drift = fmax(drift, dr);
@@ -123,18 +57,25 @@ __global__ __launch_bounds__(kBlock) void walk_real_kernel(WalkArgs a) {
 template <int N>
 hipError_t dispatch(int mode, bool drift, const WalkArgs& a, int grid, hipStream_t s) {
   const dim3 g(grid), blk(kBlock);
-  if (drift) {
+  if (a.b == 0) {  // single-term chunks (unaligned range ends); no drift to check
     switch (mode) {
-      case 0: hipLaunchKernelGGL((walk_real_kernel<N, 0, true>), g, blk, 0, s, a); break;
-      case 1: hipLaunchKernelGGL((walk_real_kernel<N, 1, true>), g, blk, 0, s, a); break;
-      case 2: hipLaunchKernelGGL((walk_real_kernel<N, 2, true>), g, blk, 0, s, a); break;
+      case 0: hipLaunchKernelGGL((walk_real_kernel<N, 0, false, true>), g, blk, 0, s, a); break;
+      case 1: hipLaunchKernelGGL((walk_real_kernel<N, 1, false, true>), g, blk, 0, s, a); break;
+      case 2: hipLaunchKernelGGL((walk_real_kernel<N, 2, false, true>), g, blk, 0, s, a); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else if (drift) {
+    switch (mode) {
+      case 0: hipLaunchKernelGGL((walk_real_kernel<N, 0, true, false>), g, blk, 0, s, a); break;
+      case 1: hipLaunchKernelGGL((walk_real_kernel<N, 1, true, false>), g, blk, 0, s, a); break;
+      case 2: hipLaunchKernelGGL((walk_real_kernel<N, 2, true, false>), g, blk, 0, s, a); break;
       default: return hipErrorInvalidValue;
     }
   } else {
     switch (mode) {
-      case 0: hipLaunchKernelGGL((walk_real_kernel<N, 0, false>), g, blk, 0, s, a); break;
-      case 1: hipLaunchKernelGGL((walk_real_kernel<N, 1, false>), g, blk, 0, s, a); break;
-      case 2: hipLaunchKernelGGL((walk_real_kernel<N, 2, false>), g, blk, 0, s, a); break;
+      case 0: hipLaunchKernelGGL((walk_real_kernel<N, 0, false, false>), g, blk, 0, s, a); break;
+      case 1: hipLaunchKernelGGL((walk_real_kernel<N, 1, false, false>), g, blk, 0, s, a); break;
+      case 2: hipLaunchKernelGGL((walk_real_kernel<N, 2, false, false>), g, blk, 0, s, a); break;
       default: return hipErrorInvalidValue;
     }
   }

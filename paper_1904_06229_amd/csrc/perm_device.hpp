@@ -22,6 +22,15 @@ typedef const __attribute__((address_space(4))) double* cdptr;
 
 __device__ __forceinline__ cdptr as_const(const double* p) { return (cdptr)(p); }
 
+// The same (uniform) pointer, hidden from the optimiser.  Without this the
+// column reads of a chunk start are loop-invariant across chunks, get hoisted
+// out of the chunk loop and stay resident -- the whole matrix in VGPRs, which
+// costs occupancy.  The empty asm emits no instruction.
+__device__ __forceinline__ const double* opaque(const double* p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
 // ---------------------------------------------------------------- gray ----
 
 __device__ __forceinline__ uint64_t gray(uint64_t k) { return k ^ (k >> 1); }
@@ -239,6 +248,7 @@ __device__ __forceinline__ void form_w_real(const double* __restrict__ staged, u
   cdptr last = as_const(staged + (N - 1) * N);
 #pragma unroll
   for (int i = 0; i < N; ++i) w[i] = last[i];
+#pragma unroll 1
   for (int j = 0; j < N - 1; ++j) {
     const double d = ((x >> j) & 1) ? 1.0 : -1.0;
     cdptr col = as_const(staged + j * N);
@@ -259,6 +269,7 @@ __device__ __forceinline__ void form_w_complex(const double* __restrict__ staged
     wr[i] = last[2 * i];
     wi[i] = last[2 * i + 1];
   }
+#pragma unroll 1
   for (int j = 0; j < N - 1; ++j) {
     const double d = ((x >> j) & 1) ? 1.0 : -1.0;
     cdptr col = as_const(staged + 2 * j * N);

@@ -91,13 +91,15 @@ hipError_t launch_batched_stage(int is_complex, const double* A, const int64_t* 
                                 const int32_t* d_n, int count, int row_scaling, double* staged,
                                 const int64_t* st_off, int32_t* rowexp_sum, int32_t* mstatus,
                                 hipStream_t s);
-hipError_t launch_batched_walk(int is_complex, int max_n, const BatchArgs& a, int grid,
+hipError_t launch_batched_walk(int is_complex, int mode, int max_n, const BatchArgs& a, int grid,
                                hipStream_t s);
 hipError_t launch_batched_reset(unsigned int* counter, hipStream_t s);
-hipError_t launch_batched_finish(int is_complex, const double* slots, const int64_t* item_first,
+hipError_t launch_batched_finish(const double* slots, const int64_t* item_first,
                                  const int32_t* item_count, const int32_t* d_n,
                                  const int32_t* rowexp_sum, const int32_t* mstatus, int count,
                                  double* d_out, int32_t* d_status, hipStream_t s);
+// Resident workgroups per CU of the persistent kernel for this configuration.
+int batched_walk_blocks_per_cu(int is_complex, int mode, int max_n);
 
 // Rows per exactly-multiplied group in the 0/1 walk: the largest k with
 // n^k < 2^50 (|2 w_i| <= n, so a group's product stays below 2^50).

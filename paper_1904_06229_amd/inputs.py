@@ -66,17 +66,36 @@ def haar_unitary(n: int, seed: int) -> np.ndarray:
     return haar_columns(n, n, rng(seed))
 
 
-def batched_haar_blocks(count: int, n_lo: int, n_hi: int, seed: int):
+def batched_haar_blocks(count: int, n_lo: int, n_hi: int, seed: int, qr=None):
     """``count`` matrices, n uniform on {n_lo..n_hi}, each the n x n top-left
-    block of an n^2-mode Haar unitary (the paper's S(n^a, n) family at a=2,
-    unscaled).  Returns (list_of_sizes, list_of_matrices)."""
+    block of an n^2-mode Haar unitary (the paper's S(n^a, n) family at a = 2,
+    unscaled, Sec. VI).
+
+    Sizes are drawn first; then, size by size in increasing order, one
+    Gaussian array for all matrices of that size and a stacked thin QR.
+    Returns (list_of_sizes, list_of_matrices) in draw order.  ``qr`` may
+    replace numpy's stacked QR (same contract: reduced Q and R of a stack).
+    """
+    qr = qr or (lambda G: np.linalg.qr(G, mode="reduced"))
     r = rng(seed)
-    sizes = r.integers(n_lo, n_hi + 1, size=count)
-    mats = []
-    for n in sizes:
-        n = int(n)
-        mats.append(haar_columns(n * n, n, r)[:n, :])
-    return [int(s) for s in sizes], mats
+    sizes = [int(x) for x in r.integers(n_lo, n_hi + 1, size=count)]
+    mats = [None] * count
+    by_n = {}
+    for k, n in enumerate(sizes):
+        by_n.setdefault(n, []).append(k)
+    for n in sorted(by_n):
+        idx = by_n[n]
+        m = n * n
+        for lo in range(0, len(idx), 2048):  # bounded memory per QR stack
+            part = idx[lo:lo + 2048]
+            g = r.standard_normal((len(part), m, n, 2))
+            G = (g[..., 0] + 1j * g[..., 1]) / np.sqrt(2.0)
+            Q, R = qr(G)
+            d = np.diagonal(R, axis1=1, axis2=2)
+            Q = Q * (d / np.abs(d))[:, None, :]
+            for t, k in enumerate(part):
+                mats[k] = np.ascontiguousarray(Q[t, :n, :])
+    return sizes, mats
 
 
 # ---- structured matrices with closed-form permanents -----------------------

@@ -1,0 +1,153 @@
+"""GPU parity of the batched path (one persistent launch over many matrices)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1904_06229_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def inp():
+    from paper_1904_06229_amd import inputs
+    return inputs
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def pack(mats, is_complex):
+    """Matrices back to back, each column-major with ld = n; offsets in doubles."""
+    parts, offs, o = [], [], 0
+    for M in mats:
+        col = np.asfortranarray(M, dtype=np.complex128 if is_complex else np.float64)
+        flat = col.ravel(order="F")
+        if is_complex:
+            flat = flat.view(np.float64)
+        parts.append(flat)
+        offs.append(o)
+        o += flat.size
+    return torch.from_numpy(np.concatenate(parts)).to("cuda"), offs
+
+
+def run_batched(B, mats, is_complex, **kw):
+    sizes = [M.shape[0] for M in mats]
+    dA, offs = pack(mats, is_complex)
+    out = torch.zeros(4 * len(mats), dtype=torch.float64, device="cuda")
+    st = torch.full((len(mats),), -1, dtype=torch.int32, device="cuda")
+    B.perm_batched(dA, sizes, offs, is_complex, out, st, **kw)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy().reshape(-1, 4)
+    vals = [complex(r[0] + r[1], r[2] + r[3]) if is_complex else r[0] + r[1] for r in o]
+    return vals, st.cpu().numpy(), (dA, sizes, offs, out, st)
+
+
+def rel(a, b):
+    return abs(a - b) / abs(b) if b != 0 else abs(a - b)
+
+
+@pytest.mark.parametrize("is_complex", [True, False])
+def test_mixed_sizes_vs_oracle(B, orc, inp, is_complex):
+    r = np.random.default_rng(11)
+    sizes = [1, 2, 3, 5, 8, 13, 17, 20, 24, 6, 9, 16, 21, 4, 12]
+    sizes += [int(x) for x in r.integers(1, 25, size=25)]
+    mats = []
+    for k, n in enumerate(sizes):
+        if is_complex:
+            mats.append(inp.complex_gaussian(n, 500 + k, scale=n ** -0.5))
+        else:
+            mats.append(inp.real_gaussian(n, 500 + k))
+    log(f"batched {'complex' if is_complex else 'real'}: {len(mats)} matrices")
+    vals, st, _ = run_batched(B, mats, is_complex)
+    assert (st == 0).all()
+    for M, v in zip(mats, vals):
+        w = orc.ryser(M)
+        want = complex(w.re.hi + w.re.lo, w.im.hi + w.im.lo) if is_complex else w.hi + w.lo
+        assert rel(v, want) < TOL, (M.shape[0], v, want)
+
+
+def test_batched_matches_single(B, inp):
+    """Same matrix (column-major A itself, not A^T), same chunks (2^8 terms):
+    the two paths walk identical chunks and differ only in reduction order."""
+    mats = [inp.complex_gaussian(n, 900 + n, scale=n ** -0.5) for n in (10, 18, 22, 24, 32)]
+    vals, st, _ = run_batched(B, mats, True, log2_chunk=8)
+    for M, v in zip(mats, vals):
+        col = torch.from_numpy(np.asfortranarray(M)).to("cuda")
+        assert col.stride(0) == 1
+        s = B.perm_complex(col, log2_chunk=8).value
+        assert rel(v, s) < 1e-15
+
+
+def test_haar_blocks_unitary_bound(B, inp):
+    sizes, mats = inp.batched_haar_blocks(200, 8, 16, seed=3)
+    vals, st, _ = run_batched(B, mats, True)
+    assert (st == 0).all()
+    assert max(abs(v) for v in vals) <= 1.0
+
+
+def test_nonfinite_flagged_per_matrix(B, inp):
+    mats = [inp.real_gaussian(n, n) for n in (5, 7, 9)]
+    mats[1][2, 3] = np.inf
+    vals, st, _ = run_batched(B, mats, False)
+    assert list(st) == [0, B.PERM_ENONFINITE, 0]
+    assert math.isnan(vals[1]) and not math.isnan(vals[0]) and not math.isnan(vals[2])
+
+
+def test_chunk_override_and_plain_fp64(B, orc, inp):
+    mats = [inp.real_gaussian(n, 40 + n) for n in (11, 15, 19)]
+    for kw in ({"log2_chunk": 1}, {"log2_chunk": 4}, {"precision": "fp64"}):
+        vals, st, _ = run_batched(B, mats, False, **kw)
+        for M, v in zip(mats, vals):
+            w = orc.ryser(M)
+            assert rel(v, w.hi + w.lo) < TOL
+
+
+def test_graph_replay_matches_eager(B, inp):
+    """Captured HIP graph: several replays, with eager work in between, each equal to eager."""
+    mats = [inp.complex_gaussian(n, 70 + n, scale=n ** -0.5) for n in (6, 14, 19, 23)]
+    eager, _, (dA, sizes, offs, out, st) = run_batched(B, mats, True)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for rep in range(4):
+            out.zero_()
+            B.perm_batched(dA, sizes, offs, True, out, st, stream=s, use_graph=True)
+            s.synchronize()
+            o = out.cpu().numpy().reshape(-1, 4)
+            got = [complex(r[0] + r[1], r[2] + r[3]) for r in o]
+            assert got == eager, f"replay {rep}"
+            # unrelated eager work between replays
+            B.perm_complex(torch.from_numpy(mats[0]).to("cuda"), stream=s)
+
+
+def test_autotune_then_batched(B, orc, inp, tmp_path):
+    path = str(tmp_path / "tune.json")
+    B.perm_autotune(True, 8, 12, path)
+    import json
+    tab = json.load(open(path))
+    assert set(tab["complex"]) == {str(n) for n in range(8, 13)}
+    mats = [inp.complex_gaussian(n, 60 + n, scale=n ** -0.5) for n in range(8, 13)]
+    vals, st, _ = run_batched(B, mats, True)
+    for M, v in zip(mats, vals):
+        w = orc.ryser(M)
+        assert rel(v, complex(w.re.hi + w.re.lo, w.im.hi + w.im.lo)) < TOL
+
+
+def test_argument_errors(B):
+    out = torch.zeros(8, dtype=torch.float64, device="cuda")
+    dA = torch.zeros(64 * 64, dtype=torch.float64, device="cuda")
+    with pytest.raises(B.PermError):
+        B.perm_batched(dA, [33], [0], False, out)
+    with pytest.raises(B.PermError):
+        B.perm_batched(dA, [4], [0], False, out, precision="split")
+    B.perm_batched(dA, [], [], False, out)  # empty batch is a no-op
