@@ -42,6 +42,42 @@ def algorithmic_ops_per_term(kind: str, n: int) -> int:
     return 2 * n
 
 
+KERNEL_SOURCES = {
+    "int01": ["kern_int01.hip"],
+    "real": ["kern_real.hip", "perm_walk.hpp"],
+    "complex": ["kern_complex.hip", "perm_walk.hpp"],
+}
+
+
+def source_sha(kind):
+    import hashlib
+    base = os.path.join(ROOT, "paper_1904_06229_amd", "csrc")
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kind] + ["perm_device.hpp", "perm_internal.hpp"]:
+        with open(os.path.join(base, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel, kind):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size), or None
+    when there is none or the kernel's source changed since it was taken."""
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    want = source_sha(kind)
+    for fn in sorted(os.listdir(pdir)):
+        with open(os.path.join(pdir, fn)) as fh:
+            for line in fh:
+                if not line.startswith("TRAFFIC "):
+                    continue
+                kv = dict(x.split("=", 1) for x in line.split()[1:])
+                if kv.get("kernel") == kernel and kv.get("src") == want:
+                    return int(kv["fetch_bytes"]) + int(kv["write_bytes"])
+    return None
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -53,6 +89,8 @@ def parse():
     p.add_argument("--blocks", type=int, default=0)
     p.add_argument("--log2-chunk", type=int, default=0)
     p.add_argument("--precision", default="dd")
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="also run a plain 256 MiB device copy (scale reference for HBM counters)")
     return p.parse_args()
 
 
@@ -215,6 +253,13 @@ def main():
     import torch
     from paper_1904_06229_amd import binding as B
 
+    if args.calibrate_copy:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")  # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     kind, n, A, desc = make_workload(args.workload)
     dA = torch.from_numpy(np.ascontiguousarray(A)).to("cuda")
     fn = {"int01": B.perm_int01, "real": B.perm_real, "complex": B.perm_complex}[kind]
@@ -252,7 +297,8 @@ def main():
         "config": {"workload": desc, "n": n, "terms": 2 ** (n - 1), "log2_chunk": r.log2_chunk,
                    "blocks": r.blocks},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                     "unit": "TOP/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                     "unit": "TOP/s", "frac": achieved / PEAK_LANE_OPS,
+                     "traffic": profiled_traffic(f"walk_{kind}_kernel<{n}>", kind),
                      "kernel": f"walk_{kind}_kernel<{n}>", "kernel_ms": kavg,
                      "ops_per_launch": alg},
     }
