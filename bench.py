@@ -33,12 +33,19 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 SEED_C2 = 20190413
 
 
-def algorithmic_ops_per_term(kind: str, n: int) -> int:
+def algorithmic_ops_per_term(kind: str, n: int, col0_nonzeros: int = 0) -> float:
     """VALU lane-operations the method needs per Gray term (App. A, subpermanent):
     n row-sum updates, n-1 multiplies, 1 signed accumulate (complex: 2n updates,
-    n-1 complex multiplies of 4 ops, 2 accumulates)."""
+    n-1 complex multiplies of 4 ops, 2 accumulates).
+
+    The pair-shared 0/1 walk evaluates the two terms of a pair as S (D1 - D0):
+    per pair m + n updates (m = ones in the flipped column), n - M - 1 static
+    multiplies (M = n // 3), 2 (M - 1) dynamic ones, one subtraction, one
+    multiply by S and one accumulate: 2n + m + M per pair."""
     if kind == "complex":
         return 2 * n + 4 * (n - 1) + 2
+    if col0_nonzeros:
+        return (2 * n + col0_nonzeros + n // 3) / 2.0
     return 2 * n
 
 
@@ -279,7 +286,7 @@ def main():
     per_perm = n * 2.0 ** (n - 1)
     value = args.steps * per_perm / dt
     kavg = sum(kms) / len(kms)
-    alg = algorithmic_ops_per_term(kind, n) * 2.0 ** (n - 1)
+    alg = algorithmic_ops_per_term(kind, n, getattr(r, "col0_nonzeros", 0)) * 2.0 ** (n - 1)
     achieved = alg / (kavg * 1e-3)
     out = {
         "metric": "Gray-code terms/sec (n*2^(n-1)/s)",
@@ -295,7 +302,8 @@ def main():
         "dtype": "f64 exact-integer + i64 bins" if kind == "int01" else "f64",
         "data": "synthetic",
         "config": {"workload": desc, "n": n, "terms": 2 ** (n - 1), "log2_chunk": r.log2_chunk,
-                   "blocks": r.blocks},
+                   "blocks": r.blocks, "walk_variant": r.walk_variant,
+                   "col0_nonzeros": r.col0_nonzeros},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                      "unit": "TOP/s", "frac": achieved / PEAK_LANE_OPS,
                      "traffic": profiled_traffic(f"walk_{kind}_kernel<{n}>", kind),

@@ -36,7 +36,8 @@ class perm_result(ctypes.Structure):
                 ("max_drift", ctypes.c_double), ("terms", ctypes.c_uint64),
                 ("chunks", ctypes.c_uint64), ("log2_chunk", ctypes.c_int32),
                 ("blocks", ctypes.c_int32), ("kernel_ms", ctypes.c_float),
-                ("total_ms", ctypes.c_float)]
+                ("total_ms", ctypes.c_float), ("walk_variant", ctypes.c_int32),
+                ("col0_nonzeros", ctypes.c_int32)]
 
 
 class perm_plan_info(ctypes.Structure):
@@ -104,6 +105,8 @@ class Result:
     blocks: int
     kernel_ms: float
     total_ms: float
+    walk_variant: int = 0
+    col0_nonzeros: int = 0
 
     @property
     def value(self):
@@ -120,7 +123,8 @@ def _result(r: perm_result, exact: bool) -> Result:
         v = (r.int_lo & ((1 << 64) - 1)) | ((r.int_hi & ((1 << 64) - 1)) << 64)
         ex = v - (1 << 128) if v >= (1 << 127) else v
     return Result(r.re_hi, r.re_lo, r.im_hi, r.im_lo, ex, r.max_drift, r.terms, r.chunks,
-                  r.log2_chunk, r.blocks, r.kernel_ms, r.total_ms)
+                  r.log2_chunk, r.blocks, r.kernel_ms, r.total_ms, r.walk_variant,
+                  r.col0_nonzeros)
 
 
 def make_opts(precision="dd", log2_chunk=0, drift_check=False, row_scaling=True, blocks=0,

@@ -20,14 +20,19 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libperm.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
+# (source, extra defines): the walk families are split by size range into two
+# translation units each so that they compile in parallel.
 SOURCES = [
-    "kern_real.hip",
-    "kern_complex.hip",
-    "kern_int01.hip",
-    "kern_stage.hip",
-    "kern_batched.hip",
-    "perm_host.cpp",
-    "perm_batched.cpp",
+    ("kern_real.hip", ["-DPERM_HALF=0"]),
+    ("kern_real.hip", ["-DPERM_HALF=1"]),
+    ("kern_complex.hip", ["-DPERM_HALF=0"]),
+    ("kern_complex.hip", ["-DPERM_HALF=1"]),
+    ("kern_int01.hip", ["-DPERM_HALF=0"]),
+    ("kern_int01.hip", ["-DPERM_HALF=1"]),
+    ("kern_stage.hip", []),
+    ("kern_batched.hip", []),
+    ("perm_host.cpp", []),
+    ("perm_batched.cpp", []),
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -38,11 +43,13 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
+def _compile(job) -> str:
+    src, defines = job
     path = os.path.join(CSRC, src)
-    obj = os.path.join(BUILD_DIR, src + ".o")
+    tag = "".join(d.replace("-D", "_").replace("=", "") for d in defines)
+    obj = os.path.join(BUILD_DIR, src + tag + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [HIPCC] + FLAGS + lang + ["-c", path, "-o", obj]
+    cmd = [HIPCC] + FLAGS + defines + lang + ["-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
@@ -51,7 +58,7 @@ def _compile(src: str) -> str:
 
 def build(jobs: int | None = None, verbose: bool = True) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s[0]))]
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, srcs))

@@ -45,21 +45,11 @@ __device__ __forceinline__ void bin_put(uint64_t& bin, uint64_t v) {
     bin -= v;
 }
 
-// Exact product of the row sums, entered into the bins with sign ADD ? + : -.
-// The entered bit patterns carry constant offsets (bits of 1.5*2^103 or of
-// 1.5*2^52) that cancel between the + and - term of a pair.
-template <int N, bool ADD>
-__device__ __forceinline__ void term_bins(const double (&r)[N], Bins& B) {
-  constexpr int k = int01_group_rows(N);
-  constexpr int K = (N + k - 1) / k;
-  double G[K];
-#pragma unroll
-  for (int g = 0; g < K; ++g) {
-    double p = r[g * k];
-#pragma unroll
-    for (int i = g * k + 1; i < (g + 1) * k && i < N; ++i) p *= r[i];
-    G[g] = p;
-  }
+// Exact product of K factors G[0..K-1] (|G| < 2^50, the last may be < 2^51),
+// entered into the bins with sign ADD ? + : -.  The entered bit patterns carry
+// constant offsets (bits of 1.5*2^103 or of 1.5*2^52; see product_offsets).
+template <int K, bool ADD>
+__device__ __forceinline__ void product_bins(const double (&G)[K], Bins& B) {
   if constexpr (K == 1) {
     bin_put<ADD>(B.b0, bits(G[0] + kM52));
   } else {
@@ -136,16 +126,45 @@ __device__ __forceinline__ void term_bins(const double (&r)[N], Bins& B) {
   }
 }
 
-// Offsets carried by one term's entries (per bin), for single-term chunks.
-template <int N>
-__device__ __forceinline__ Bins term_offsets() {
+// Product of rows [lo, hi) (exact when its bound is below 2^53).
+template <int N, int LO, int HI>
+__device__ __forceinline__ double rows_prod(const double (&r)[N]) {
+  double p = r[LO];
+#pragma unroll
+  for (int i = LO + 1; i < HI; ++i) p *= r[i];
+  return p;
+}
+
+// Exact product of all row sums, in groups of int01_group_rows(N) rows.
+template <int N, bool ADD>
+__device__ __forceinline__ void term_bins(const double (&r)[N], Bins& B) {
   constexpr int k = int01_group_rows(N);
   constexpr int K = (N + k - 1) / k;
+  double G[K];
+#pragma unroll
+  for (int g = 0; g < K; ++g) {
+    double p = r[g * k];
+#pragma unroll
+    for (int i = g * k + 1; i < (g + 1) * k && i < N; ++i) p *= r[i];
+    G[g] = p;
+  }
+  product_bins<K, ADD>(G, B);
+}
+
+// Offsets carried by one product_bins<K> call (per bin).
+template <int K>
+__device__ __forceinline__ Bins product_offsets() {
   const uint64_t c = bits(kC51), m = bits(kM52);
   if constexpr (K == 1) return Bins{m, 0, 0};
   if constexpr (K == 2) return Bins{m, c, 0};
   if constexpr (K == 3) return Bins{m, c + m, c};
   return Bins{m, c + m, c + m};
+}
+
+template <int N>
+__device__ __forceinline__ Bins term_offsets() {
+  constexpr int k = int01_group_rows(N);
+  return product_offsets<(N + k - 1) / k>();
 }
 
 __device__ __forceinline__ u128 fold(const Bins& B) {
@@ -218,14 +237,81 @@ __device__ __forceinline__ u128 walk_chunk(const double* __restrict__ staged, ui
   return fold(B);
 }
 
-template <int N, bool DRIFT, bool SINGLE>
+// ----------------------------------------------------------- pair-shared ----
+// For a 0/1 matrix staged with its sparsest column first (column 0, the one
+// flipped between the two terms of every pair) and that column's m nonzero
+// rows on top, rows M..N-1 (M = N/3 >= m) do not change between the terms of
+// a pair.  With S their product and D0, D1 the products of rows 0..M-1 before
+// and after the flip, the pair contributes P1 - P0 = S (D1 - D0): S and the
+// exact combination are formed once per pair instead of twice, and the
+// column-0 update touches M rows instead of N.  The staging kernel checks
+// that m <= M and that the degrees of rows 0..M-1 multiply to less than 2^50
+// (so D0, D1 and D1 - D0 are exact); otherwise this variant does nothing and
+// the plain walk runs.
+template <int N>
+constexpr int pair_rows() {
+  return N / 3;
+}
+
+template <int N, int M, int KS>
+__device__ __forceinline__ void pair_bins(double (&r)[N], const double* __restrict__ staged,
+                                          uint32_t sub0, Bins& B) {
+  constexpr int k = int01_group_rows(N);
+  double G[KS + 1];
+#pragma unroll
+  for (int g = 0; g < KS; ++g) {
+    const int lo = M + g * k;
+    double p = r[lo];
+#pragma unroll
+    for (int i = lo + 1; i < lo + k && i < N; ++i) p *= r[i];
+    G[g] = p;
+  }
+  const double D0 = rows_prod<N, 0, M>(r);
+  cdptr col = as_const(staged + sub0 * (N * N));  // column 0; zero below row M
+#pragma unroll
+  for (int i = 0; i < M; ++i) r[i] += col[i];
+  const double D1 = rows_prod<N, 0, M>(r);
+  G[KS] = D1 - D0;
+  product_bins<KS + 1, true>(G, B);
+}
+
+template <int N>
+__device__ __forceinline__ u128 walk_chunk_pairs(const double* __restrict__ staged, uint64_t G,
+                                                 int b, uint32_t gpar) {
+  constexpr int M = pair_rows<N>();
+  constexpr int k = int01_group_rows(N);
+  constexpr int KS = (N - M + k - 1) / k;
+  staged = opaque(staged);
+  double r[N];
+  form_w_real<N>(staged, G << b, r);
+  Bins B{0, 0, 0};
+  const uint32_t half = 1u << (b - 1);
+  uint32_t t = 0;
+  for (; t + 1 < half; ++t) {
+    pair_bins<N, M, KS>(r, staged, t & 1u, B);
+    const uint32_t s1 = 2 * t + 2;
+    const int j = __builtin_ctz(s1);
+    add_col<N>(r, staged, flip_subtracts(s1, j, b, gpar), j);
+  }
+  pair_bins<N, M, KS>(r, staged, (b >= 2) ? (t & 1u) : gpar, B);
+  // every pair entered its bit patterns with a + sign: remove the offsets
+  const Bins off = product_offsets<KS + 1>();
+  B.b0 -= (uint64_t)half * off.b0;
+  B.b1 -= (uint64_t)half * off.b1;
+  B.b2 -= (uint64_t)half * off.b2;
+  return fold(B);
+}
+
+// VARIANT 0: plain walk; VARIANT 1: pair-shared walk.  status[1] (set by the
+// staging kernel) says which one the matrix allows; the other exits at once.
+template <int N, bool DRIFT, bool SINGLE, int VARIANT>
 __global__ __launch_bounds__(kBlock) void walk_int01_kernel(WalkArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint64_t wave = wave_id();
   const uint64_t nwaves = (uint64_t)gridDim.x * kWavesPerBlock;
   u128 acc{0, 0};
   double drift = 0.0;
-  if (a.status[0] == kStOk) {
+  if (a.status[0] == kStOk && a.status[1] == VARIANT) {
     for (uint64_t task = wave; task < a.ntasks; task += nwaves) {
       const uint64_t c = task_chunk(task, lane);
       const uint32_t gpar = (uint32_t)((a.first + (task & 1)) & 1);
@@ -233,6 +319,8 @@ __global__ __launch_bounds__(kBlock) void walk_int01_kernel(WalkArgs a) {
       u128 part;
       if constexpr (SINGLE)
         part = single_term<N>(a.staged, a.first + c);
+      else if constexpr (VARIANT == 1)
+        part = walk_chunk_pairs<N>(a.staged, a.first + c, a.b, gpar);
       else
         part = walk_chunk<N, DRIFT>(a.staged, a.first + c, a.b, gpar, dr);
       if (c < a.nchunks) {
@@ -256,14 +344,22 @@ __global__ __launch_bounds__(kBlock) void walk_int01_kernel(WalkArgs a) {
 }
 
 template <int N>
-hipError_t dispatch(bool drift, const WalkArgs& a, int grid, hipStream_t s) {
+hipError_t dispatch(bool drift, int variant, const WalkArgs& a, int grid, hipStream_t s) {
   const dim3 g(grid), blk(kBlock);
-  if (a.b == 0)
-    hipLaunchKernelGGL((walk_int01_kernel<N, false, true>), g, blk, 0, s, a);
-  else if (drift)
-    hipLaunchKernelGGL((walk_int01_kernel<N, true, false>), g, blk, 0, s, a);
-  else
-    hipLaunchKernelGGL((walk_int01_kernel<N, false, false>), g, blk, 0, s, a);
+  if (variant == 1) {
+    if constexpr (pair_rows<N>() >= kInt01PairMinRows) {
+      if (a.b == 0 || drift) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((walk_int01_kernel<N, false, false, 1>), g, blk, 0, s, a);
+    } else {
+      return hipErrorInvalidValue;
+    }
+  } else if (a.b == 0) {
+    hipLaunchKernelGGL((walk_int01_kernel<N, false, true, 0>), g, blk, 0, s, a);
+  } else if (drift) {
+    hipLaunchKernelGGL((walk_int01_kernel<N, true, false, 0>), g, blk, 0, s, a);
+  } else {
+    hipLaunchKernelGGL((walk_int01_kernel<N, false, false, 0>), g, blk, 0, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -271,11 +367,22 @@ hipError_t dispatch(bool drift, const WalkArgs& a, int grid, hipStream_t s) {
 
 #define PERM_CASE(N) \
   case N:            \
-    return dispatch<N>(drift, a, grid, s);
+    return dispatch<N>(drift, variant, a, grid, s);
 
-hipError_t launch_walk_int01(int n, bool drift, const WalkArgs& a, int grid, hipStream_t s) {
+// Compiled twice: PERM_HALF = 0 instantiates n = 1..32, PERM_HALF = 1 n = 33..64
+// (two translation units that build in parallel).
+#if PERM_HALF == 0
+#define PERM_LAUNCH launch_walk_int01_lo
+#define PERM_CASES "perm_cases_lo.inc"
+#else
+#define PERM_LAUNCH launch_walk_int01_hi
+#define PERM_CASES "perm_cases_hi.inc"
+#endif
+
+hipError_t PERM_LAUNCH(int n, bool drift, int variant, const WalkArgs& a, int grid,
+                             hipStream_t s) {
   switch (n) {
-#include "perm_cases.inc"
+#include PERM_CASES
     default:
       return hipErrorInvalidValue;
   }

@@ -88,10 +88,20 @@ hipError_t dispatch(int mode, bool drift, const WalkArgs& a, int grid, hipStream
   case N:            \
     return dispatch<N>(mode, drift, a, grid, s);
 
-hipError_t launch_walk_real(int n, int mode, bool drift, const WalkArgs& a, int grid,
+// Compiled twice: PERM_HALF = 0 instantiates n = 1..32, PERM_HALF = 1 n = 33..64
+// (two translation units that build in parallel).
+#if PERM_HALF == 0
+#define PERM_LAUNCH launch_walk_real_lo
+#define PERM_CASES "perm_cases_lo.inc"
+#else
+#define PERM_LAUNCH launch_walk_real_hi
+#define PERM_CASES "perm_cases_hi.inc"
+#endif
+
+hipError_t PERM_LAUNCH(int n, int mode, bool drift, const WalkArgs& a, int grid,
                             hipStream_t s) {
   switch (n) {
-#include "perm_cases.inc"
+#include PERM_CASES
     default:
       return hipErrorInvalidValue;
   }

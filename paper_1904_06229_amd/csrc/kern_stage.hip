@@ -10,7 +10,7 @@
 //
 // Finishing (one workgroup): adds the per-workgroup partial sums of all walk
 // launches in a fixed order (thread t takes partials t, t+256, ...; then the
-// 256 thread sums are added in thread order), so the result is bit-for-bit
+// 256 thread sums are added along a fixed binary tree), so the result is bit-for-bit
 // reproducible (the paper stores partial sums in an array before the final
 // compensated sum instead of reducing them in arbitrary order, Sec. II.B).
 #include "perm_device.hpp"
@@ -87,44 +87,87 @@ __global__ __launch_bounds__(kBlock) void stage_float_kernel(const double* __res
 // checks (n-1) + sum_i log2(d_i!)/d_i < 127 (Bregman: per(A) <=
 // prod_i (d_i!)^(1/d_i)), which keeps 2^(n-1) per(A) inside a signed 128-bit
 // integer.
+//
+// With pair_rows = M > 0 (full permanents only: a permutation changes the
+// terms, not the total) the copy is permuted: the column with the fewest
+// ones becomes column 0 (the column flipped between the two terms of every
+// pair), the rows with a one there come first, then the other rows by
+// ascending degree.  status[1] = 1 when that column has at most M ones and
+// the first M rows' degrees multiply to less than 2^50, i.e. when the
+// pair-shared walk is exact; status[2] = the number of ones in column 0.
 __global__ __launch_bounds__(kBlock) void stage_int01_kernel(const uint8_t* __restrict__ A, int n,
                                                              int ld, int range_check,
-                                                             double* staged, double* rowabs,
-                                                             int32_t* rowexp, int32_t* status,
-                                                             double* bound) {
-  __shared__ int32_t s_bad;
+                                                             int pair_rows, double* staged,
+                                                             double* rowabs, int32_t* rowexp,
+                                                             int32_t* status, double* bound) {
+  __shared__ uint8_t s_a[kMaxN * kMaxN];  // s_a[i * kMaxN + j] = a_ij
+  __shared__ int32_t s_row[kMaxN], s_col[kMaxN], s_deg[kMaxN], s_csum[kMaxN];
   __shared__ double s_term[kMaxN];
-  __shared__ int32_t s_zero;
+  __shared__ int32_t s_bad;
   const int tid = threadIdx.x;
-  if (tid == 0) {
-    s_bad = 0;
-    s_zero = 0;
-  }
+  if (tid == 0) s_bad = 0;
   __syncthreads();
   const int nn = n * n;
   for (int idx = tid; idx < nn; idx += kBlock) {
     const int i = idx % n, j = idx / n;
     const uint8_t v = A[(size_t)i + (size_t)j * ld];
     if (v > 1) atomicOr(&s_bad, 1);
-    staged[idx] = 2.0 * v;
-    staged[nn + idx] = -2.0 * v;
+    s_a[i * kMaxN + j] = v;
   }
+  __syncthreads();
+  // row sums and Bregman terms (threads 0..n-1), column sums (threads 64..64+n-1)
   if (tid < n) {
-    const int i = tid;
     int d = 0;
-    for (int j = 0; j < n; ++j) d += A[(size_t)i + (size_t)j * ld] ? 1 : 0;
-    rowabs[i] = (double)d;
-    rowexp[i] = 0;
+    for (int j = 0; j < n; ++j) d += s_a[tid * kMaxN + j];
+    s_deg[tid] = d;
     double lf = 0.0;
     for (int k = 2; k <= d; ++k) lf += log2((double)k);
-    s_term[i] = d > 0 ? lf / d : 0.0;
-    if (d == 0) atomicOr(&s_zero, 1);
+    s_term[tid] = d > 0 ? lf / d : 0.0;
+    s_row[tid] = tid;
+    s_col[tid] = tid;
+  } else if (tid >= kMaxN && tid < kMaxN + n) {
+    const int j = tid - kMaxN;
+    int c = 0;
+    for (int i = 0; i < n; ++i) c += s_a[i * kMaxN + j];
+    s_csum[j] = c;
   }
   __syncthreads();
   if (tid == 0) {
-    double bsum = 0.0;
-    for (int i = 0; i < n; ++i) bsum += s_term[i];
-    const double lb = s_zero ? 0.0 : (double)(n - 1) + bsum;
+    int pairs_ok = 0, ones0 = 0;
+    if (pair_rows > 0 && !s_bad) {
+      int best = 0;
+      for (int j = 1; j < n; ++j)
+        if (s_csum[j] < s_csum[best]) best = j;
+      ones0 = s_csum[best];
+      s_col[0] = best;
+      for (int j = 0, q = 1; j < n; ++j)
+        if (j != best) s_col[q++] = j;
+      int q = 0;
+      for (int i = 0; i < n; ++i)
+        if (s_a[i * kMaxN + best]) s_row[q++] = i;
+      const int top = q;
+      for (int i = 0; i < n; ++i)
+        if (!s_a[i * kMaxN + best]) {  // insertion by ascending degree (stable)
+          int p = q++;
+          while (p > top && s_deg[s_row[p - 1]] > s_deg[i]) {
+            s_row[p] = s_row[p - 1];
+            --p;
+          }
+          s_row[p] = i;
+        }
+      if (ones0 <= pair_rows) {
+        double prod = 1.0;  // exact while below 2^53; only compared with 2^50
+        for (int i = 0; i < pair_rows && i < n; ++i) prod *= (double)s_deg[s_row[i]];
+        pairs_ok = prod < 1125899906842624.0 ? 1 : 0;
+      }
+    }
+    double lb = 0.0;
+    bool zero_row = false;
+    for (int i = 0; i < n; ++i) {
+      if (s_deg[i] == 0) zero_row = true;
+      lb += s_term[i];
+    }
+    lb = zero_row ? 0.0 : (double)(n - 1) + lb;
     bound[0] = lb;
     int32_t st = kStOk;
     if (s_bad)
@@ -132,7 +175,30 @@ __global__ __launch_bounds__(kBlock) void stage_int01_kernel(const uint8_t* __re
     else if (range_check && lb >= 127.0)
       st = kStRange;
     status[0] = st;
+    status[1] = pairs_ok;
+    status[2] = ones0;
   }
+  __syncthreads();
+  for (int idx = tid; idx < nn; idx += kBlock) {
+    const int i = idx % n, j = idx / n;  // staged position (row i, column j)
+    const double v = 2.0 * s_a[s_row[i] * kMaxN + s_col[j]];
+    staged[idx] = v;
+    staged[nn + idx] = -v;
+  }
+  if (tid < n) {
+    rowabs[tid] = (double)s_deg[s_row[tid]];
+    rowexp[tid] = 0;
+  }
+}
+
+template <class T, class Add>
+__device__ __forceinline__ T tree_sum(T* s, Add add) {
+  // fixed binary tree over kBlock values in shared memory; thread 0 gets the sum
+  for (int stride = kBlock / 2; stride > 0; stride >>= 1) {
+    if ((int)threadIdx.x < stride) s[threadIdx.x] = add(s[threadIdx.x], s[threadIdx.x + stride]);
+    __syncthreads();
+  }
+  return s[0];
 }
 
 template <int KIND>
@@ -165,18 +231,23 @@ __global__ __launch_bounds__(kBlock) void finish_kernel(const void* __restrict__
     }
     if (want_drift) dr = fmax(dr, drift_part[k]);
   }
-  s_re[tid] = re;
-  s_im[tid] = im;
-  s_i[tid] = iv;
-  s_dr[tid] = dr;
-  __syncthreads();
+  if constexpr (KIND == kInt01) {
+    s_i[tid] = iv;
+    __syncthreads();
+    iv = tree_sum(s_i, u128_add);
+  } else {
+    s_re[tid] = re;
+    if constexpr (KIND == kComplex) s_im[tid] = im;
+    __syncthreads();
+    re = tree_sum(s_re, dd_add);
+    if constexpr (KIND == kComplex) im = tree_sum(s_im, dd_add);
+  }
+  if (want_drift) {
+    s_dr[tid] = dr;
+    __syncthreads();
+    dr = tree_sum(s_dr, [](double x, double y) { return fmax(x, y); });
+  }
   if (tid == 0) {
-    for (int t = 1; t < kBlock; ++t) {
-      re = dd_add(re, s_re[t]);
-      im = dd_add(im, s_im[t]);
-      iv = u128_add(iv, s_i[t]);
-      dr = fmax(dr, s_dr[t]);
-    }
     int32_t es = 0;
     for (int i = 0; i < n; ++i) es += rowexp[i];
     res->v[0] = re.hi;
@@ -189,18 +260,19 @@ __global__ __launch_bounds__(kBlock) void finish_kernel(const void* __restrict__
     res->status = status[0];
     res->exp_sum = es;
     res->bound = bound ? bound[0] : 0.0;
-    res->pad = 0.0;
+    res->variant = KIND == kInt01 ? status[1] : 0;
+    res->ones0 = KIND == kInt01 ? status[2] : 0;
   }
 }
 
 }  // namespace
 
 hipError_t launch_stage(int kind, const void* A, int n, int ld, int row_scaling, int range_check,
-                        double* staged, double* rowabs, int32_t* rowexp, int32_t* status,
-                        double* bound, hipStream_t s) {
+                        int pair_rows, double* staged, double* rowabs, int32_t* rowexp,
+                        int32_t* status, double* bound, hipStream_t s) {
   if (kind == kInt01) {
     hipLaunchKernelGGL(stage_int01_kernel, dim3(1), dim3(kBlock), 0, s, (const uint8_t*)A, n, ld,
-                       range_check, staged, rowabs, rowexp, status, bound);
+                       range_check, pair_rows, staged, rowabs, rowexp, status, bound);
   } else {
     hipLaunchKernelGGL(stage_float_kernel, dim3(1), dim3(kBlock), 0, s, (const double*)A, n, ld,
                        kind == kComplex ? 1 : 0, row_scaling, staged, rowabs, rowexp, status);

@@ -129,10 +129,14 @@ uint64_t total_terms(int n) { return n >= 64 ? (1ull << 63) : (1ull << (n - 1));
 int floor_log2(uint64_t x) { return x ? 63 - __builtin_clzll(x) : -1; }
 
 // Automatic chunk length: enough chunks to give every SIMD several waves
-// (2^18 lane chunks), chunks no longer than the cap.
+// (2^18 lane chunks), chunks no longer than the cap, and at least 2^4 terms
+// (when the range has them) so that small sizes walk instead of forming
+// every term from scratch.
 int auto_log2_chunk(uint64_t count, int cap) {
-  int b = floor_log2(count) - 18;
-  if (b < 0) b = 0;
+  const int lg = floor_log2(count);
+  int b = lg - 18;
+  const int lo = lg < 4 ? (lg > 0 ? lg : 0) : 4;
+  if (b < lo) b = lo;
   if (b > cap) b = cap;
   return b;
 }
@@ -165,22 +169,29 @@ struct Raw {
   int blocks;
 };
 
-perm_status launch_walk(int kind, int n, int mode, bool drift, const WalkArgs& a, int grid,
-                        hipStream_t s) {
+perm_status launch_walk(int kind, int n, int mode, bool drift, int variant, const WalkArgs& a,
+                        int grid, hipStream_t s) {
   hipError_t e;
+  const bool lo = n <= 32;
   if (kind == kReal)
-    e = launch_walk_real(n, mode, drift, a, grid, s);
+    e = lo ? launch_walk_real_lo(n, mode, drift, a, grid, s)
+           : launch_walk_real_hi(n, mode, drift, a, grid, s);
   else if (kind == kComplex)
-    e = launch_walk_complex(n, mode, drift, a, grid, s);
+    e = lo ? launch_walk_complex_lo(n, mode, drift, a, grid, s)
+           : launch_walk_complex_hi(n, mode, drift, a, grid, s);
   else
-    e = launch_walk_int01(n, drift, a, grid, s);
+    e = lo ? launch_walk_int01_lo(n, drift, variant, a, grid, s)
+           : launch_walk_int01_hi(n, drift, variant, a, grid, s);
   if (e != hipSuccess) return fail(PERM_EHIP, std::string("walk launch failed: ") + hipGetErrorString(e));
   return PERM_OK;
 }
 
 // Stage, walk [start, start+count), finish, and bring the record back.
+// full: the range is the whole sum, so the 0/1 path may permute rows and
+// columns and use the pair-shared walk.
 perm_status run_range(int kind, const void* dA, int n, int ld, uint64_t start, uint64_t count,
-                      const perm_opts* opts, int range_check, hipStream_t s, Raw* raw) {
+                      const perm_opts* opts, int range_check, bool full, hipStream_t s,
+                      Raw* raw) {
   perm_opts o{};
   if (opts) o = *opts;
   const int is_int = kind == kInt01;
@@ -190,19 +201,28 @@ perm_status run_range(int kind, const void* dA, int n, int ld, uint64_t start, u
   Workspace* ws = nullptr;
   st = get_workspace(&ws);
   if (st != PERM_OK) return st;
-  const int cap = o.blocks > 0 ? o.blocks : 4 * ws->cu_count;
+  // 8 workgroups (32 waves) per CU: more than can be resident, so the
+  // dispatcher hands out the remaining workgroups as others finish, which
+  // evens out the tail.
+  const int cap = o.blocks > 0 ? o.blocks : 8 * ws->cu_count;
   const bool drift = o.drift_check != 0;
   const int mode = is_int ? 0 : o.precision;
 
+  const int pair_rows = (is_int && full && !drift && plan.log2_chunk >= 1 &&
+                         plan.head_count == 0 && plan.tail_count == 0 &&
+                         n / 3 >= kInt01PairMinRows)
+                            ? n / 3
+                            : 0;
   HIP_TRY(hipEventRecord(ws->ev[0], s));
-  HIP_TRY(launch_stage(kind, dA, n, ld, o.no_row_scaling ? 0 : 1, range_check, ws->staged,
-                       ws->rowabs, ws->rowexp, ws->status, ws->bound, s));
+  HIP_TRY(launch_stage(kind, dA, n, ld, o.no_row_scaling ? 0 : 1, range_check, pair_rows,
+                       ws->staged, ws->rowabs, ws->rowexp, ws->status, ws->bound, s));
 
   int nparts = 0;
   int body_grid = 0;
   char* part_base = (char*)ws->partials;
   const size_t part_bytes = (kind == kComplex) ? 32 : 16;
-  auto walk = [&](uint64_t first, uint64_t nchunks, int b, int* grid_out) -> perm_status {
+  auto walk = [&](uint64_t first, uint64_t nchunks, int b, int variant,
+                  int* grid_out) -> perm_status {
     if (nchunks == 0) return PERM_OK;
     WalkArgs a;
     a.staged = ws->staged;
@@ -218,14 +238,20 @@ perm_status run_range(int kind, const void* dA, int n, int ld, uint64_t start, u
     const int grid = grid_for(a.ntasks, cap);
     if (grid_out) *grid_out = grid;
     nparts += grid;
-    return launch_walk(kind, n, mode, drift, a, grid, s);
+    return launch_walk(kind, n, mode, drift, variant, a, grid, s);
   };
 
   HIP_TRY(hipEventRecord(ws->ev[1], s));
-  if ((st = walk(plan.head_start, plan.head_count, 0, nullptr)) != PERM_OK) return st;
-  if ((st = walk(plan.body_first_chunk, plan.body_chunks, plan.log2_chunk, &body_grid)) != PERM_OK)
+  if ((st = walk(plan.head_start, plan.head_count, 0, 0, nullptr)) != PERM_OK) return st;
+  if ((st = walk(plan.body_first_chunk, plan.body_chunks, plan.log2_chunk, 0, &body_grid)) !=
+      PERM_OK)
     return st;
-  if ((st = walk(plan.tail_start, plan.tail_count, 0, nullptr)) != PERM_OK) return st;
+  // Pair-shared 0/1 walk: launched next to the plain one; the staging kernel's
+  // flag makes exactly one of the two do the work.
+  if (pair_rows > 0 &&
+      (st = walk(plan.body_first_chunk, plan.body_chunks, plan.log2_chunk, 1, nullptr)) != PERM_OK)
+    return st;
+  if ((st = walk(plan.tail_start, plan.tail_count, 0, 0, nullptr)) != PERM_OK) return st;
   HIP_TRY(hipEventRecord(ws->ev[2], s));
   HIP_TRY(launch_finish(kind, ws->partials, nparts, ws->drift, drift ? 1 : 0, ws->status,
                         ws->rowexp, n, ws->bound, ws->dres, s));
@@ -249,6 +275,8 @@ void fill_common(const Raw& raw, uint64_t count, perm_result* out) {
   out->blocks = raw.blocks;
   out->kernel_ms = raw.kernel_ms;
   out->total_ms = raw.total_ms;
+  out->walk_variant = raw.r.variant;
+  out->col0_nonzeros = raw.r.variant ? raw.r.ones0 : 0;
 }
 
 perm_status status_from_device(int32_t st) {
@@ -289,7 +317,7 @@ perm_status float_call(int kind, const double* dA, int n, int ld, const perm_opt
   if (!dA) return fail(PERM_EINVAL, "dA is NULL");
   const uint64_t T = total_terms(n);
   Raw raw;
-  st = run_range(kind, dA, n, ld, 0, T, opts, 0, (hipStream_t)stream, &raw);
+  st = run_range(kind, dA, n, ld, 0, T, opts, 0, true, (hipStream_t)stream, &raw);
   if (st != PERM_OK) return st;
   st = status_from_device(raw.r.status);
   if (st != PERM_OK) return st;
@@ -377,7 +405,7 @@ perm_status perm_int01(const uint8_t* dA, int n, int ld, const perm_opts* opts, 
   if (!dA) return fail(PERM_EINVAL, "dA is NULL");
   const uint64_t T = total_terms(n);
   Raw raw;
-  st = run_range(kInt01, dA, n, ld, 0, T, opts, 1, (hipStream_t)stream, &raw);
+  st = run_range(kInt01, dA, n, ld, 0, T, opts, 1, true, (hipStream_t)stream, &raw);
   if (st != PERM_OK) return st;
   st = status_from_device(raw.r.status);
   if (st != PERM_OK) return st;
@@ -417,7 +445,7 @@ perm_status perm_partial(int dtype, const void* dA, int n, int ld, uint64_t star
     return PERM_OK;
   }
   Raw raw;
-  st = run_range(kind, dA, n, ld, start, count, opts, 0, (hipStream_t)stream, &raw);
+  st = run_range(kind, dA, n, ld, start, count, opts, 0, false, (hipStream_t)stream, &raw);
   if (st != PERM_OK) return st;
   st = status_from_device(raw.r.status);
   if (st != PERM_OK) return st;

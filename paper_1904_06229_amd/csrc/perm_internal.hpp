@@ -44,21 +44,39 @@ struct DevResult {
   int32_t status;
   int32_t exp_sum;    // sum of row-scaling exponents
   double bound;       // 0/1 path: log2 accumulator bound
-  double pad;
+  int32_t variant;    // 0/1 path: 1 if the pair-shared walk ran
+  int32_t ones0;      // 0/1 path: ones in the staged column 0
 };
 
 enum Kind { kReal = 0, kComplex = 1, kInt01 = 2 };
 
-hipError_t launch_walk_real(int n, int mode, bool drift, const WalkArgs& a, int grid,
-                            hipStream_t s);
-hipError_t launch_walk_complex(int n, int mode, bool drift, const WalkArgs& a, int grid,
+// Each walk family is built as two translation units (n <= 32 and n > 32);
+// the launch_walk_* dispatchers in perm_host.cpp pick one by n.
+hipError_t launch_walk_real_lo(int n, int mode, bool drift, const WalkArgs& a, int grid,
                                hipStream_t s);
-hipError_t launch_walk_int01(int n, bool drift, const WalkArgs& a, int grid, hipStream_t s);
+hipError_t launch_walk_real_hi(int n, int mode, bool drift, const WalkArgs& a, int grid,
+                               hipStream_t s);
+hipError_t launch_walk_complex_lo(int n, int mode, bool drift, const WalkArgs& a, int grid,
+                                  hipStream_t s);
+hipError_t launch_walk_complex_hi(int n, int mode, bool drift, const WalkArgs& a, int grid,
+                                  hipStream_t s);
+hipError_t launch_walk_int01_lo(int n, bool drift, int variant, const WalkArgs& a, int grid,
+                                hipStream_t s);
+hipError_t launch_walk_int01_hi(int n, bool drift, int variant, const WalkArgs& a, int grid,
+                                hipStream_t s);
+// 0/1 walk variant 0: plain exact walk; 1: pair-shared walk (the staging
+// kernel's status[1] decides at run time which of the two launched variants
+// works).
+// Smallest pair_rows (n/3) for which the pair-shared 0/1 walk is built.
+constexpr int kInt01PairMinRows = 3;
 
 // Staging: validate A, choose row exponents, write +A/-A (0/1: +2A/-2A).
+// 0/1 input with pair_rows > 0: the matrix is permuted (sparsest column
+// first, its nonzero rows on top, then rows by ascending degree) and status[1]
+// is set to 1 when the pair-shared walk with that many dynamic rows is exact.
 hipError_t launch_stage(int kind, const void* A, int n, int ld, int row_scaling, int range_check,
-                        double* staged, double* rowabs, int32_t* rowexp, int32_t* status,
-                        double* bound, hipStream_t s);
+                        int pair_rows, double* staged, double* rowabs, int32_t* rowexp,
+                        int32_t* status, double* bound, hipStream_t s);
 
 // Fixed-order sum of the per-workgroup partials into a DevResult.
 hipError_t launch_finish(int kind, const void* partials, int nparts, const double* drift_part,

@@ -34,6 +34,14 @@ def dev(A):
     return torch.from_numpy(np.ascontiguousarray(A)).to("cuda")
 
 
+def dev_cm(A):
+    """Column-major device copy: the library sees A itself (a row-major tensor
+    is read as A^T, which has the same permanent but other terms)."""
+    t = torch.from_numpy(np.asfortranarray(A)).to("cuda")
+    assert t.dim() < 2 or t.shape[0] < 2 or t.stride(0) == 1
+    return t
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -94,8 +102,43 @@ def test_int01_config_30x30(B, orc, inp):
     log("int01 30x30 workload")
     got = B.perm_int01(dev(A))
     want = orc.ryser(A)
-    log(f"  per = {want}, kernel {got.kernel_ms:.3f} ms")
+    log(f"  per = {want}, kernel {got.kernel_ms:.3f} ms, walk variant {got.walk_variant}")
     assert got.exact == want
+    assert got.walk_variant == 1  # sparsest column has 10 = n/3 ones
+
+
+def with_sparse_column(rng, n, ones, p=0.5):
+    """0/1 matrix with iid Bernoulli(p) entries, column 5 replaced by exactly `ones` ones."""
+    A = (rng.random((n, n)) < p).astype(np.uint8)
+    col = np.zeros(n, dtype=np.uint8)
+    col[rng.choice(n, ones, replace=False)] = 1
+    A[:, 5] = col
+    return A
+
+
+@pytest.mark.parametrize("n", [9, 12, 18, 21, 24, 26])
+def test_int01_pair_shared_walk(B, orc, inp, n):
+    """The pair-shared walk (sparsest column first; rows that column does not
+    touch share one product per pair) engages exactly when that column has at
+    most n/3 ones; both walks are exact."""
+    rng = np.random.default_rng(7000 + n)
+    M = n // 3
+    for ones, engaged in ((M, True), (max(M - 2, 1), True), (M + 1, None)):
+        A = with_sparse_column(rng, n, ones)
+        want = orc.ryser(A)
+        got = B.perm_int01(dev_cm(A))
+        assert got.exact == want, (n, ones)
+        plain = B.perm_int01(dev_cm(A), drift_check=True)  # drift check keeps the plain walk
+        assert plain.exact == want and plain.walk_variant == 0
+        if engaged:
+            assert got.walk_variant == 1, (n, ones)
+        elif (A.sum(axis=0) > M).all():
+            assert got.walk_variant == 0
+
+
+def test_int01_pair_shared_not_for_dense(B, inp):
+    r = B.perm_int01(dev(inp.ones(20)))
+    assert r.walk_variant == 0 and r.exact == math.factorial(20)
 
 
 # -------------------------------------------------------- structured ----
