@@ -12,7 +12,9 @@ Printed: one JSON line with the throughput, the roofline of the walk kernel
 issue peak; the kernel's own duration comes from HIP events recorded by the
 library on the launch stream), and the CPU oracle timed on the host cores.
 
-Other workloads (--workload c1|c3|c5|c4) are for manual runs.
+Other workloads (--workload c1|c3|c5|c4) are for manual runs; c5 (48x48
+real, 2^47 terms, minutes per permanent) runs as 16 perm_partial slices with
+a progress line each.
 """
 from __future__ import annotations
 
@@ -96,6 +98,12 @@ def parse():
     p.add_argument("--blocks", type=int, default=0)
     p.add_argument("--log2-chunk", type=int, default=0)
     p.add_argument("--precision", default="dd")
+    p.add_argument("--slices", type=int, default=0,
+                   help="evaluate each permanent as this many perm_partial slices, a progress "
+                        "line per slice (c5 uses 16 unless given)")
+    p.add_argument("--checkpoint", default=None, help="slice checkpoint file (resume)")
+    p.add_argument("--terms-log2", type=int, default=0,
+                   help="time only the first 2^K Gray terms (perm_partial); labelled as a prefix")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run a plain 256 MiB device copy (scale reference for HBM counters)")
     return p.parse_args()
@@ -135,12 +143,19 @@ def cpu_baseline(kind, n, A):
         frac = count / float(1 << n)
         sample = f"integer Ryser over {count} of the 2^{n} subsets ({frac:.3g} of one permanent)"
     else:
-        # direct half-range terms (O(n^2) each) over a prefix of the Gray range
-        count = 1 << 14
-        t0 = time.perf_counter()
-        oracle.chunk_partial(A, 0, count, threads=threads)
-        dt = time.perf_counter() - t0
-        frac = count / float(1 << (n - 1))
+        # direct half-range terms (O(n^2) each) over a prefix of the Gray range,
+        # doubled until the sample takes about 10 s (or covers the whole range)
+        T = 1 << (n - 1)
+        count = min(1 << 14, T)
+        while True:
+            t0 = time.perf_counter()
+            oracle.chunk_partial(A, 0, count, threads=threads)
+            dt = time.perf_counter() - t0
+            if dt >= 5.0 or count >= T:
+                break
+            grow = 2 ** max(1, min(8, int(math.log2(10.0 / max(dt, 1e-4)))))
+            count = min(T, count * grow)
+        frac = count / float(T)
         sample = f"{count} Gray terms formed directly (long double), {frac:.3g} of one permanent"
     value = frac * n * 2.0 ** (n - 1) / dt
     return {"value": value, "unit": "n*2^(n-1)/s", "cores": threads, "kind": "oracle",
@@ -249,6 +264,65 @@ def bench_batched(args):
     print(json.dumps(outj))
 
 
+def bench_sliced(args):
+    """Each step is one whole permanent as consecutive perm_partial slices
+    (a progress line per slice on stderr); slice sums are added in slice order."""
+    import numpy as np
+    import torch
+    from paper_1904_06229_amd import longrun
+
+    kind, n, A, desc = make_workload(args.workload)
+    dA = torch.from_numpy(np.asfortranarray(A)).to("cuda")
+    slices = args.slices or 16
+    kw = dict(blocks=args.blocks, log2_chunk=args.log2_chunk)
+    if kind != "int01":
+        kw["precision"] = args.precision
+
+    def prog(m):
+        print(m, file=sys.stderr, flush=True)
+
+    kms, value, t_all = [], None, 0.0
+    for step in range(args.warmup + args.steps):
+        prog(f"step {step + 1}/{args.warmup + args.steps} ({'warmup' if step < args.warmup else 'timed'})")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        value, info = longrun.run_sliced(dA, slices=slices, progress=prog,
+                                         checkpoint=args.checkpoint, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if step >= args.warmup:
+            t_all += dt
+            kms.extend(info["kernel_ms"])
+    terms = 2 ** (n - 1)
+    per_perm = n * float(terms)
+    alg = algorithmic_ops_per_term(kind, n) * float(terms) / slices
+    kavg = sum(kms) / len(kms) if kms else float("nan")
+    if isinstance(value, tuple):
+        res = repr(complex(float(value[0]), float(value[1])))
+    else:
+        res = repr(float(value))
+    out = {
+        "metric": "Gray-code terms/sec (n*2^(n-1)/s)",
+        "value": args.steps * per_perm / t_all, "unit": "n*2^(n-1)/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_all * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc + f", whole permanent as {slices} slices of "
+                                      f"{terms // slices} terms",
+                   "n": n, "terms": terms, "slices": slices, "precision": args.precision},
+        "roofline": {"bound": "alu", "achieved": alg / (kavg * 1e-3) / 1e12,
+                     "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
+                     "frac": alg / (kavg * 1e-3) / PEAK_LANE_OPS,
+                     "traffic": profiled_traffic(f"walk_{kind}_kernel<{n}>", kind),
+                     "kernel": f"walk_{kind}_kernel<{n}>", "kernel_ms": kavg,
+                     "ops_per_launch": alg},
+        "result": res,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(kind, n, A)
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -256,6 +330,8 @@ def main():
         sys.exit(2)
     if args.workload == "c4":
         return bench_batched(args)
+    if args.slices or args.checkpoint or (args.workload == "c5" and not args.terms_log2):
+        return bench_sliced(args)
     import numpy as np
     import torch
     from paper_1904_06229_amd import binding as B
@@ -273,6 +349,12 @@ def main():
     kw = dict(blocks=args.blocks, log2_chunk=args.log2_chunk)
     if kind != "int01":
         kw["precision"] = args.precision
+    terms = 2 ** (n - 1)
+    if args.terms_log2:
+        terms = 2 ** min(args.terms_log2, n - 1)
+        desc += f" -- PREFIX ONLY: first {terms} of the 2^{n - 1} Gray terms (perm_partial)"
+        dAcm = dA.t().contiguous().t()
+        fn = (lambda X, **k: B.perm_partial(dAcm, 0, terms, **k))
     for _ in range(args.warmup):
         r = fn(dA, **kw)
     torch.cuda.synchronize()
@@ -283,10 +365,10 @@ def main():
         kms.append(r.kernel_ms)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    per_perm = n * 2.0 ** (n - 1)
+    per_perm = n * float(terms)
     value = args.steps * per_perm / dt
     kavg = sum(kms) / len(kms)
-    alg = algorithmic_ops_per_term(kind, n, getattr(r, "col0_nonzeros", 0)) * 2.0 ** (n - 1)
+    alg = algorithmic_ops_per_term(kind, n, getattr(r, "col0_nonzeros", 0)) * float(terms)
     achieved = alg / (kavg * 1e-3)
     out = {
         "metric": "Gray-code terms/sec (n*2^(n-1)/s)",
@@ -301,7 +383,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64 exact-integer + i64 bins" if kind == "int01" else "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "n": n, "terms": 2 ** (n - 1), "log2_chunk": r.log2_chunk,
+        "config": {"workload": desc, "n": n, "terms": terms, "log2_chunk": r.log2_chunk,
                    "blocks": r.blocks, "walk_variant": r.walk_variant,
                    "col0_nonzeros": r.col0_nonzeros},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
