@@ -15,6 +15,11 @@ arrays through ctypes.  Routes (see the C file for the passages they follow):
 * ``ryser_range``   -- the raw signed Ryser sum over a subset-index range.
 * ``chunk_partial`` -- App. A ``subpermanent`` partial sum over a Gray-index
                        range, each term formed directly (no walk).
+* ``ryser2``        -- Ryser's formula for repeated columns (Sec. II.A,
+                       Eq. ryser2) from the distinct columns and their
+                       multiplicities; ``ryser2_range`` is its raw sum over a
+                       range of the reflected mixed-radix Gray order, and
+                       ``mixed_gray`` unranks that order.
 
 Real results come back as :class:`Pair` (an unevaluated double pair hi + lo
 holding the long-double value), complex ones as :class:`CPair`, integer ones
@@ -72,6 +77,9 @@ def _load():
         "oracle_chunk_complex": ([dp, i, i, u64, u64, i, dp]),
         "oracle_chunk_int": ([bp, i, i, u64, u64, i, up]),
         "oracle_default_threads": ([]),
+        "oracle_ryser2": ([dp, i, i, i, ctypes.POINTER(ctypes.c_int), i, i, dp]),
+        "oracle_ryser2_range": ([dp, i, i, i, ctypes.POINTER(ctypes.c_int), i, u64, u64, i, dp]),
+        "oracle_mixed_gray": ([u64, i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -207,6 +215,55 @@ def chunk_partial(A, g0: int, count: int, threads: int = 0):
          "int": lib.oracle_chunk_int}[kind]
     _check(f(_ptr(M, kind), n, n, g0, count, threads, out), "chunk_partial")
     return _result(kind, out)
+
+
+def _prep_rep(C, mult):
+    C = np.asarray(C)
+    if C.ndim != 2:
+        raise ValueError("C must be n x R")
+    n, R = C.shape
+    if len(mult) != R:
+        raise ValueError("one multiplicity per column of C")
+    m = (ctypes.c_int * max(R, 1))(*[int(x) for x in mult])
+    if np.iscomplexobj(C):
+        return np.asfortranarray(C, dtype=np.complex128), n, R, m, 1
+    return np.asfortranarray(C, dtype=np.float64), n, R, m, 0
+
+
+def _rep_result(cplx, out):
+    if cplx:
+        return CPair(Pair(out[0], out[1]), Pair(out[2], out[3]))
+    return Pair(out[0], out[1])
+
+
+def ryser2(C, mult, threads: int = 0):
+    """per(A) by Eq. ryser2, A having column k of C repeated mult[k] times."""
+    lib = _load()
+    M, n, R, m, cplx = _prep_rep(C, mult)
+    out = (ctypes.c_double * 4)()
+    _check(lib.oracle_ryser2(M.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n, R, n, m,
+                             cplx, threads, out), "ryser2")
+    return _rep_result(cplx, out)
+
+
+def ryser2_range(C, mult, g0: int, count: int, threads: int = 0):
+    """Raw Eq. ryser2 sum (no (-1)^n) over reflected mixed-radix Gray indices [g0, g0+count)."""
+    lib = _load()
+    M, n, R, m, cplx = _prep_rep(C, mult)
+    out = (ctypes.c_double * 4)()
+    _check(lib.oracle_ryser2_range(M.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n, R, n,
+                                   m, cplx, g0, count, threads, out), "ryser2_range")
+    return _rep_result(cplx, out)
+
+
+def mixed_gray(g: int, radices):
+    """Digits (digit 0 fastest) of index g in the reflected mixed-radix Gray order."""
+    lib = _load()
+    R = len(radices)
+    r = (ctypes.c_int * R)(*[int(x) for x in radices])
+    f = (ctypes.c_int * R)()
+    _check(lib.oracle_mixed_gray(g, R, r, f), "mixed_gray")
+    return [int(x) for x in f]
 
 
 def default_threads() -> int:

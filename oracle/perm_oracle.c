@@ -31,6 +31,15 @@
  *                          walk, so there is no drift.  Sign convention as in
  *                          App. A: term g carries (-1)^(g+1), and
  *                          per(A) = 2 (-1)^n * (sum over all 2^(n-1) terms).
+ *   O5 oracle_ryser2_*     Ryser's formula for a matrix whose columns repeat
+ *                          (Sec. II.A, Eq. ryser2): distinct columns c_k with
+ *                          multiplicities m_k, a sum over all vectors f with
+ *                          0 <= f_k <= m_k of (-1)^(sum f) prod_k C(m_k, f_k)
+ *                          prod_i sum_k f_k c_k(i), per = (-1)^n * sum.  The
+ *                          whole sum runs over f in counting order; the range
+ *                          form runs over f in reflected mixed-radix Gray
+ *                          order (the paper fixes no order for Eq. ryser2),
+ *                          every term formed directly from f.
  *
  * Threads (pthreads) only split index ranges evenly (App. A, distribute);
  * every thread's partial result lands in an array that is added in index
@@ -649,6 +658,210 @@ int oracle_chunk_int(const uint8_t* B, int n, int ld, uint64_t g0, uint64_t coun
   u128 S = 0;
   for (int t = 0; t < T; ++t) S += jobs[t].acc;
   u128_to_pair(S, out);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O5: Ryser's formula with repeated columns (Sec. II.A, Eq. ryser2)         */
+/* ------------------------------------------------------------------------ */
+
+/* Binomial coefficients C(m, f), m <= 64, from Pascal's rule in exact 64-bit
+ * integers (C(64, 32) < 2^64); long double holds every one of them exactly. */
+static uint64_t g_binom[ORACLE_MAX_N + 1][ORACLE_MAX_N + 1];
+static pthread_once_t g_binom_once = PTHREAD_ONCE_INIT;
+
+static void binom_init(void) {
+  for (int m = 0; m <= ORACLE_MAX_N; ++m) {
+    g_binom[m][0] = 1;
+    for (int f = 1; f <= m; ++f)
+      g_binom[m][f] = g_binom[m - 1][f - 1] + (f <= m - 1 ? g_binom[m - 1][f] : 0);
+  }
+}
+
+/* Reflected mixed-radix Gray code, digit 0 changing fastest: the sequence for
+ * digits j..0 takes digit j through 0, 1, ..., r_j - 1, and under each value v
+ * runs the sequence of digits j-1..0, forwards for even v and backwards for
+ * odd v.  Q[j] = r_0 r_1 ... r_{j-1} is the length of that lower sequence.
+ * Unranking follows the definition from the top digit down. */
+static void mixed_gray_unrank(uint64_t g, int R, const uint64_t* Q, int* f) {
+  uint64_t pos = g;
+  for (int j = R - 1; j >= 0; --j) {
+    const uint64_t v = pos / Q[j];
+    const uint64_t rem = pos % Q[j];
+    f[j] = (int)v;
+    pos = (v & 1) ? Q[j] - 1 - rem : rem;
+  }
+}
+
+/* Counting order: f_k is digit k of g in the mixed radix (m_k + 1). */
+static void counting_unrank(uint64_t g, int R, const int* m, int* f) {
+  for (int k = 0; k < R; ++k) {
+    f[k] = (int)(g % (uint64_t)(m[k] + 1));
+    g /= (uint64_t)(m[k] + 1);
+  }
+}
+
+typedef struct {
+  const double* C;
+  const int* m;
+  const uint64_t* Q;
+  int n, R, ld, cplx, gray_order;
+  uint64_t g0, len;
+  long double re, im;
+} rep_job;
+
+static void* ryser2_worker(void* arg) {
+  rep_job* jb = (rep_job*)arg;
+  const int n = jb->n, R = jb->R, ld = jb->ld;
+  int f[ORACLE_MAX_N];
+  kahan_ld Sr = {0.0L, 0.0L}, Si = {0.0L, 0.0L};
+  for (uint64_t g = jb->g0; g < jb->g0 + jb->len; ++g) {
+    if (jb->gray_order)
+      mixed_gray_unrank(g, R, jb->Q, f);
+    else
+      counting_unrank(g, R, jb->m, f);
+    int fsum = 0;
+    long double wgt = 1.0L;
+    for (int k = 0; k < R; ++k) {
+      fsum += f[k];
+      wgt *= (long double)g_binom[jb->m[k]][f[k]];
+    }
+    long double pr = 1.0L, pi = 0.0L;
+    for (int i = 0; i < n; ++i) {
+      long double sr = 0.0L, si = 0.0L;
+      for (int k = 0; k < R; ++k) {
+        if (jb->cplx) {
+          size_t o = 2 * (i + (size_t)k * ld);
+          sr += (long double)f[k] * (long double)jb->C[o];
+          si += (long double)f[k] * (long double)jb->C[o + 1];
+        } else {
+          sr += (long double)f[k] * (long double)jb->C[i + (size_t)k * ld];
+        }
+      }
+      long double nr = pr * sr - pi * si;
+      long double ni = pr * si + pi * sr;
+      pr = nr;
+      pi = ni;
+    }
+    if (fsum & 1) wgt = -wgt;
+    kahan_add(&Sr, wgt * pr);
+    kahan_add(&Si, wgt * pi);
+  }
+  jb->re = Sr.s;
+  jb->im = Si.s;
+  return NULL;
+}
+
+/* Checks the arguments, fills Q and the number of vectors f (T). */
+static int ryser2_setup(int n, int R, int ld, const int* m, uint64_t* Q, uint64_t* T) {
+  if (n < 1 || n > ORACLE_MAX_N || R < 1 || R > n || ld < n || !m) return 0;
+  int total = 0;
+  u128 t = 1;
+  for (int k = 0; k < R; ++k) {
+    if (m[k] < 1) return 0;
+    total += m[k];
+    Q[k] = (uint64_t)t;
+    t *= (u128)(m[k] + 1);
+    if (t > ((u128)1 << 63)) return 0;
+  }
+  if (total != n) return 0;
+  *T = (uint64_t)t;
+  pthread_once(&g_binom_once, binom_init);
+  return 1;
+}
+
+static void ryser2_run(rep_job* proto, uint64_t g0, uint64_t count, int nthreads,
+                       long double* re, long double* im) {
+  rep_job jobs[ORACLE_MAX_THREADS];
+  pthread_t th[ORACLE_MAX_THREADS];
+  int T = pick_threads(nthreads, count);
+  for (int t = 0; t < T; ++t) {
+    jobs[t] = *proto;
+    uint64_t off, len;
+    distribute(count, (uint64_t)T, (uint64_t)t, &off, &len);
+    jobs[t].g0 = g0 + off;
+    jobs[t].len = len;
+  }
+  int started = 0;
+  for (int t = 0; t < T; ++t) {
+    if (pthread_create(&th[t], NULL, ryser2_worker, &jobs[t]) != 0) break;
+    ++started;
+  }
+  for (int t = started; t < T; ++t) ryser2_worker(&jobs[t]);
+  for (int t = 0; t < started; ++t) pthread_join(th[t], NULL);
+  kahan_ld Sr = {0.0L, 0.0L}, Si = {0.0L, 0.0L};
+  for (int t = 0; t < T; ++t) {
+    kahan_add(&Sr, jobs[t].re);
+    kahan_add(&Si, jobs[t].im);
+  }
+  *re = Sr.s;
+  *im = Si.s;
+}
+
+/* per(A) for the n x n matrix A whose columns are c_k repeated m_k times
+ * (k < R, sum m_k = n); C is n x R column-major (complex: interleaved).
+ * out: [re hi, re lo, im hi, im lo]. */
+int oracle_ryser2(const double* C, int n, int R, int ld, const int* m, int cplx, int nthreads,
+                  double* out) {
+  uint64_t Q[ORACLE_MAX_N], T;
+  if (!ryser2_setup(n, R, ld, m, Q, &T)) return -1;
+  rep_job proto;
+  memset(&proto, 0, sizeof proto);
+  proto.C = C;
+  proto.m = m;
+  proto.Q = Q;
+  proto.n = n;
+  proto.R = R;
+  proto.ld = ld;
+  proto.cplx = cplx;
+  long double re, im;
+  ryser2_run(&proto, 0, T, nthreads, &re, &im);
+  if (n & 1) {
+    re = -re;
+    im = -im;
+  }
+  ld_to_pair(re, out);
+  ld_to_pair(im, out + 2);
+  return 0;
+}
+
+/* The raw sum of Eq. ryser2 (without (-1)^n) over Gray indices
+ * [g0, g0 + count) of the reflected mixed-radix order. */
+int oracle_ryser2_range(const double* C, int n, int R, int ld, const int* m, int cplx,
+                        uint64_t g0, uint64_t count, int nthreads, double* out) {
+  uint64_t Q[ORACLE_MAX_N], T;
+  if (!ryser2_setup(n, R, ld, m, Q, &T)) return -1;
+  if (g0 > T || count > T - g0) return -1;
+  rep_job proto;
+  memset(&proto, 0, sizeof proto);
+  proto.C = C;
+  proto.m = m;
+  proto.Q = Q;
+  proto.n = n;
+  proto.R = R;
+  proto.ld = ld;
+  proto.cplx = cplx;
+  proto.gray_order = 1;
+  long double re, im;
+  ryser2_run(&proto, g0, count, nthreads, &re, &im);
+  ld_to_pair(re, out);
+  ld_to_pair(im, out + 2);
+  return 0;
+}
+
+/* Digits f_0..f_{R-1} of Gray index g (radices r_k), for tests of the order. */
+int oracle_mixed_gray(uint64_t g, int R, const int* radix, int* f) {
+  uint64_t Q[ORACLE_MAX_N];
+  if (R < 1 || R > ORACLE_MAX_N) return -1;
+  u128 t = 1;
+  for (int k = 0; k < R; ++k) {
+    if (radix[k] < 1) return -1;
+    Q[k] = (uint64_t)t;
+    t *= (u128)radix[k];
+    if (t > ((u128)1 << 63)) return -1;
+  }
+  if ((u128)g >= t) return -1;
+  mixed_gray_unrank(g, R, Q, f);
   return 0;
 }
 
