@@ -179,6 +179,46 @@ perm_status perm_batched(const double* dA, const int32_t* h_n, const int64_t* h_
 perm_status perm_autotune(int is_complex, int n_lo, int n_hi, const char* cache_path,
                           void* stream);
 
+/*
+ * perm_repeated -- per(A) of an n x n matrix whose columns repeat (Sec. II.A,
+ * Eq. ryser2): A has mult[k] copies of column k of C (k < R, sum mult = n), in
+ * any order.  With f ranging over the vectors 0 <= f_k <= mult[k],
+ *
+ *     per(A) = (-1)^n sum_f (-1)^(f_1+...+f_R) prod_k C(mult[k], f_k)
+ *                          prod_i sum_k f_k c_ik,
+ *
+ * prod_k (mult[k] + 1) terms instead of 2^(n-1).  Repeated rows: per(A) =
+ * per(A^T), so pass the distinct rows as the columns of C.
+ *   dC      device pointer to C, n x R, column-major with leading dimension
+ *           ld >= n (dtype PERM_DT_REAL: doubles; PERM_DT_COMPLEX: interleaved
+ *           pairs).  PERM_DT_INT01 is not accepted (pass 0/1 data as doubles).
+ *   mult    HOST array of R multiplicities, each >= 1, summing to n.
+ *   1 <= R <= n <= 64 and prod_k (mult[k] + 1) <= 2^63.
+ *   The vectors f are walked in reflected mixed-radix Gray order (digit k =
+ *   f_k, digit 0 changing fastest), so every step changes one f_k by +-1 and
+ *   adds or subtracts one column of C.  A lane walks a chunk that runs the
+ *   first b digits through all their values (L = (mult[0]+1)...(mult[b-1]+1)
+ *   terms, b chosen so that L <= 2^log2_chunk, automatic when 0, at most 2^14);
+ *   out->log2_chunk reports b.  Precision: PERM_FP64_DD only; drift_check is
+ *   not provided (PERM_ENOTIMPL).  Row scaling as for perm_real.
+ * Errors: PERM_EINVAL (sizes, multiplicities, options), PERM_ENONFINITE,
+ *   PERM_ENOTIMPL, PERM_EHIP.
+ */
+perm_status perm_repeated(int dtype, const double* dC, int n, int R, int ld,
+                          const int32_t* mult, const perm_opts* opts, perm_result* out,
+                          void* stream);
+
+/*
+ * perm_repeated_partial -- the sum of Eq. ryser2 over Gray indices
+ * [start, start + count) of that order, without the factor (-1)^n:
+ *   sum_{g} (-1)^(sum f) prod_k C(mult[k], f_k) prod_i sum_k f_k c_ik,  f = f(g),
+ * start + count <= prod_k (mult[k] + 1).  Ranges need not be aligned to chunks.
+ * Arguments and errors as perm_repeated.
+ */
+perm_status perm_repeated_partial(int dtype, const double* dC, int n, int R, int ld,
+                                  const int32_t* mult, uint64_t start, uint64_t count,
+                                  const perm_opts* opts, perm_result* out, void* stream);
+
 /* Chunk plan for a Gray-index range, computed on the host (no GPU needed). */
 typedef struct {
   int32_t log2_chunk;      /* L = 2^log2_chunk */

@@ -56,6 +56,10 @@ SIGNATURES = {
     "perm_partial": ([_i, _vp, _i, _i, _u64, _u64, ctypes.POINTER(perm_opts),
                       ctypes.POINTER(perm_result), _vp], _i),
     "perm_batched": ([_vp, _vp, _vp, _i, _i, ctypes.POINTER(perm_opts), _vp, _vp, _vp], _i),
+    "perm_repeated": ([_i, _vp, _i, _i, _i, ctypes.POINTER(ctypes.c_int32),
+                       ctypes.POINTER(perm_opts), ctypes.POINTER(perm_result), _vp], _i),
+    "perm_repeated_partial": ([_i, _vp, _i, _i, _i, ctypes.POINTER(ctypes.c_int32), _u64, _u64,
+                               ctypes.POINTER(perm_opts), ctypes.POINTER(perm_result), _vp], _i),
     "perm_autotune": ([_i, _i, _i, ctypes.c_char_p, _vp], _i),
     "perm_plan": ([_i, _u64, _u64, _i, _i, ctypes.POINTER(perm_plan_info)], _i),
     "perm_int01_bound": ([ctypes.POINTER(ctypes.c_int32), _i], ctypes.c_double),
@@ -220,6 +224,50 @@ def perm_partial(A, start: int, count: int, stream=None, **opts) -> Result:
     _check(_lib.perm_partial(dt, p, n, ld, int(start), int(count), ctypes.byref(o),
                              ctypes.byref(r), _stream_handle(stream)), "perm_partial")
     return _result(r, kind == "int01")
+
+
+def _distinct_columns(C, mult):
+    """(dtype code, pointer, n, R, ld, multiplicity array) for an n x R device
+    tensor of distinct columns; a row-major tensor is copied to column-major
+    (C is not square, so the transpose is not an option)."""
+    import torch
+    if not isinstance(C, torch.Tensor) or C.device.type != "cuda":
+        raise TypeError("expected a CUDA (HIP) torch tensor")
+    if C.dtype == torch.float64:
+        dt = PERM_DT_REAL
+    elif C.dtype == torch.complex128:
+        dt = PERM_DT_COMPLEX
+    else:
+        raise TypeError(f"expected float64 or complex128, got {C.dtype}")
+    if C.dim() != 2:
+        raise ValueError("C must be n x R")
+    n, R = C.shape
+    if len(mult) != R:
+        raise ValueError("one multiplicity per column of C")
+    if n > 1 and C.stride(0) != 1:
+        C = C.t().contiguous().t()
+    ld = C.stride(1) if R > 1 else max(n, 1)
+    m = (ctypes.c_int32 * max(R, 1))(*[int(x) for x in mult])
+    return dt, ctypes.c_void_p(C.data_ptr()), n, R, max(ld, n, 1), m, C
+
+
+def perm_repeated(C, mult, stream=None, **opts) -> Result:
+    """per(A), A having column k of C repeated mult[k] times (Eq. ryser2)."""
+    dt, p, n, R, ld, m, keep = _distinct_columns(C, mult)
+    o, r = make_opts(**opts), perm_result()
+    _check(_lib.perm_repeated(dt, p, n, R, ld, m, ctypes.byref(o), ctypes.byref(r),
+                              _stream_handle(stream)), "perm_repeated")
+    return _result(r, False)
+
+
+def perm_repeated_partial(C, mult, start: int, count: int, stream=None, **opts) -> Result:
+    """Raw Eq. ryser2 sum (no (-1)^n) over reflected mixed-radix Gray indices [start, start+count)."""
+    dt, p, n, R, ld, m, keep = _distinct_columns(C, mult)
+    o, r = make_opts(**opts), perm_result()
+    _check(_lib.perm_repeated_partial(dt, p, n, R, ld, m, int(start), int(count), ctypes.byref(o),
+                                      ctypes.byref(r), _stream_handle(stream)),
+           "perm_repeated_partial")
+    return _result(r, False)
 
 
 def perm_batched(A_packed, sizes, offsets, is_complex: bool, out, status=None, stream=None,

@@ -1,0 +1,261 @@
+// Walk of Ryser's formula for repeated columns (Sec. II.A, Eq. ryser2).
+//
+// Term of the vector f: (-1)^(f_0+...+f_{R-1}) prod_k C(m_k, f_k)
+// prod_i w_i, w_i = sum_k f_k c_ik.  The vectors are taken in reflected
+// mixed-radix Gray order, so from one term to the next a single f_j moves by
+// one and w changes by +-c_j: n additions per term, as in the binary walk of
+// App. A.  One lane walks one chunk (a full run of the inner digits, L terms);
+// the digit j, its direction and the inner weight at step s come from the
+// staged tables (wave-uniform: all chunks of a wave have the same parity), and
+// column c_j is read with scalar loads.  The outer digits are formed afresh
+// from the chunk index at every chunk start, so the walk's rounding does not
+// carry over from chunk to chunk; their weight and sign multiply the chunk sum.
+//
+// Per term: n FP64 additions (complex 2n), the product of the row sums, one
+// multiply by the inner weight, and a double-double lane sum per pair of terms.
+#include "perm_device.hpp"
+
+namespace perm {
+namespace {
+
+typedef const __attribute__((address_space(4))) int32_t* ciptr;
+
+#if PERM_CPLX
+constexpr int kCw = 2;
+#else
+constexpr int kCw = 1;
+#endif
+
+struct Acc {
+  dd re, im;
+};
+
+// Row sums of one term or chunk start.
+template <int N>
+struct Rows {
+  double r[N];
+#if PERM_CPLX
+  double i[N];
+#endif
+};
+
+template <int N>
+__device__ __forceinline__ void add_col(Rows<N>& w, const double* staged, int32_t off) {
+  cdptr col = as_const(staged + off);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    w.r[i] += col[kCw * i];
+#if PERM_CPLX
+    w.i[i] += col[kCw * i + 1];
+#endif
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void add_col_times(Rows<N>& w, const double* staged, int k,
+                                              double f) {
+  cdptr col = as_const(staged + kCw * k * N);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    w.r[i] = fma(f, col[kCw * i], w.r[i]);
+#if PERM_CPLX
+    w.i[i] = fma(f, col[kCw * i + 1], w.i[i]);
+#endif
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void product(const Rows<N>& w, double& pr, double& pi) {
+#if PERM_CPLX
+  prod_c64<N>(w.r, w.i, pr, pi);
+#else
+  pr = prod_f64<N>(w.r);
+  pi = 0.0;
+#endif
+}
+
+// Digits k = k0 .. R-1 of q (q = chunk index with k0 = b, or term index with
+// k0 = 0): f_k = a_k or r_k - 1 - a_k by the parity of the digits above
+// (a_k the counting digit); adds f_k c_k to the row sums and multiplies the
+// weight by C(m_k, f_k).  Returns the parity of the digit sum.
+template <int N>
+__device__ __forceinline__ uint32_t outer_digits(const RepArgs& a, const double* staged,
+                                                 uint64_t q, int k0, Rows<N>& w, double& W) {
+  ciptr radix = (ciptr)a.radix;
+  uint32_t odd = 0;
+#pragma unroll 1
+  for (int k = k0; k < a.R; ++k) {
+    const uint32_t r = (uint32_t)radix[k];
+    const uint64_t qn = q / r;
+    const uint32_t dgt = (uint32_t)(q - qn * r);
+    q = qn;
+    const uint32_t f = (q & 1) ? r - 1u - dgt : dgt;
+    odd ^= f & 1u;
+    W *= a.binom[k * kRepBinomStride + f];
+    add_col_times<N>(w, staged, k, (double)f);
+  }
+  return odd;
+}
+
+// Exact product of a double-double by a double (TwoProduct on the high part).
+__device__ __forceinline__ dd dd_scale(dd x, double s) {
+  const double h = x.hi * s;
+  const double e = fma(x.hi, s, -h);
+  return dd{h, fma(x.lo, s, e)};
+}
+
+template <int N>
+__device__ __forceinline__ Acc single_term(const RepArgs& a, uint64_t g) {
+  const double* staged = opaque(a.staged);
+  Rows<N> w;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    w.r[i] = 0.0;
+#if PERM_CPLX
+    w.i[i] = 0.0;
+#endif
+  }
+  double W = 1.0;
+  const uint32_t odd = outer_digits<N>(a, staged, g, 0, w, W);
+  if (odd) W = -W;
+  double pr, pi;
+  product<N>(w, pr, pi);
+  const double hr = W * pr, hi = W * pi;
+  return Acc{{hr, fma(W, pr, -hr)}, {hi, fma(W, pi, -hi)}};
+}
+
+template <int N>
+__device__ __forceinline__ Acc walk_chunk(const RepArgs& a, uint64_t c, uint32_t par) {
+  const double* staged = opaque(a.staged);
+  Rows<N> w;
+  {
+    cdptr st = as_const(staged + kCw * (2 * (a.R + 1) + (int)par) * N);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      w.r[i] = st[kCw * i];
+#if PERM_CPLX
+      w.i[i] = st[kCw * i + 1];
+#endif
+    }
+  }
+  double W = 1.0;
+  const uint32_t odd = outer_digits<N>(a, staged, c, a.b, w, W);
+  cdptr tin = as_const(a.tin + par * (uint32_t)a.L);
+  ciptr toff = (ciptr)(a.toff + par * (uint32_t)a.L);
+  Acc acc{{0.0, 0.0}, {0.0, 0.0}};
+  const int L = a.L;
+  int s = 0;
+  for (; s + 1 < L; s += 2) {
+    const double t0 = tin[s], t1 = tin[s + 1];
+    const int32_t o0 = toff[s], o1 = toff[s + 1];
+    double p0r, p0i, p1r, p1i;
+    product<N>(w, p0r, p0i);
+    add_col<N>(w, staged, o0);
+    product<N>(w, p1r, p1i);
+    add_col<N>(w, staged, o1);
+    dd_acc(acc.re, fma(t1, p1r, t0 * p0r));
+#if PERM_CPLX
+    dd_acc(acc.im, fma(t1, p1i, t0 * p0i));
+#endif
+  }
+  if (s < L) {  // odd L: the last term has no partner
+    double pr, pi;
+    product<N>(w, pr, pi);
+    dd_acc(acc.re, tin[s] * pr);
+#if PERM_CPLX
+    dd_acc(acc.im, tin[s] * pi);
+#endif
+  }
+  if (odd) W = -W;
+  return Acc{dd_scale(acc.re, W), dd_scale(acc.im, W)};
+}
+
+template <int N, bool SINGLE>
+__global__ __launch_bounds__(kBlock) void rep_walk_kernel(RepArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint64_t wave = wave_id();
+  const uint64_t nwaves = (uint64_t)gridDim.x * kWavesPerBlock;
+  dd re{0.0, 0.0}, im{0.0, 0.0};
+  if (a.status[0] == kStOk) {
+    for (uint64_t task = wave; task < a.ntasks; task += nwaves) {
+      const uint64_t c = task_chunk(task, lane);
+      Acc part;
+      if constexpr (SINGLE) {
+        part = single_term<N>(a, a.first + c);
+      } else {
+        const uint32_t par = (uint32_t)((a.first + (task & 1)) & 1);
+        part = walk_chunk<N>(a, a.first + c, par);
+      }
+      if (c < a.nchunks) {
+        re = dd_add(re, part.re);
+#if PERM_CPLX
+        im = dd_add(im, part.im);
+#endif
+      }
+    }
+  }
+  const dd br = block_sum(wave_sum(re), dd_add);
+  double* out = (double*)a.partials;
+#if PERM_CPLX
+  __syncthreads();
+  const dd bi = block_sum(wave_sum(im), dd_add);
+  if (threadIdx.x == 0) {
+    out[4 * blockIdx.x] = br.hi;
+    out[4 * blockIdx.x + 1] = br.lo;
+    out[4 * blockIdx.x + 2] = bi.hi;
+    out[4 * blockIdx.x + 3] = bi.lo;
+  }
+#else
+  (void)im;
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = br.hi;
+    out[2 * blockIdx.x + 1] = br.lo;
+  }
+#endif
+}
+
+template <int N>
+hipError_t dispatch(bool single, const RepArgs& a, int grid, hipStream_t s) {
+  if (single)
+    hipLaunchKernelGGL((rep_walk_kernel<N, true>), dim3(grid), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL((rep_walk_kernel<N, false>), dim3(grid), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define PERM_CASE(N) \
+  case N:            \
+    return dispatch<N>(single, a, grid, s);
+
+// Built four times: PERM_CPLX selects real or complex, PERM_HALF the sizes
+// n = 1..32 or n = 33..64.
+#if PERM_CPLX
+#if PERM_HALF == 0
+#define PERM_LAUNCH launch_rep_walk_complex_lo
+#else
+#define PERM_LAUNCH launch_rep_walk_complex_hi
+#endif
+#else
+#if PERM_HALF == 0
+#define PERM_LAUNCH launch_rep_walk_real_lo
+#else
+#define PERM_LAUNCH launch_rep_walk_real_hi
+#endif
+#endif
+#if PERM_HALF == 0
+#define PERM_CASES "perm_cases_lo.inc"
+#else
+#define PERM_CASES "perm_cases_hi.inc"
+#endif
+
+hipError_t PERM_LAUNCH(int n, bool single, const RepArgs& a, int grid, hipStream_t s) {
+  switch (n) {
+#include PERM_CASES
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace perm

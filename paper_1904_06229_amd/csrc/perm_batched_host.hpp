@@ -1,9 +1,12 @@
-// Host side of the batched path (perm_batched, perm_autotune).
+// Host-side helpers shared by the runtime files: release of the batched
+// (perm_batched, perm_autotune) and repeated-column (perm_repeated) workspaces,
+// and the thread-local error text.
 #pragma once
 
 #include "../../include/perm.h"
 
 namespace perm {
 void batched_release();
+void repeated_release();
 perm_status set_error(perm_status s, const char* msg);
 }  // namespace perm

@@ -499,6 +499,7 @@ void perm_release(void) {
   }
   g_ws.clear();
   perm::batched_release();
+  perm::repeated_release();
   (void)hipSetDevice(cur);
 }
 

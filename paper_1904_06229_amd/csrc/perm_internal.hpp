@@ -119,6 +119,49 @@ hipError_t launch_batched_finish(const double* slots, const int64_t* item_first,
 // Resident workgroups per CU of the persistent kernel for this configuration.
 int batched_walk_blocks_per_cu(int is_complex, int mode, int max_n);
 
+// ------------------------------------------------------ repeated columns ----
+// Eq. ryser2 walk (perm_repeated): the vectors f (0 <= f_k <= m_k) in
+// reflected mixed-radix Gray order, radix r_k = m_k + 1, digit 0 fastest.
+// A chunk is one run of the first b digits through all L = r_0...r_{b-1}
+// values, i.e. Gray indices [c L, (c+1) L).  Inside it the digit changed at
+// step s, its direction, and the weight of the inner digits depend only on s
+// and the parity of c (tables tin/toff, built by the staging kernel); the
+// lane -> chunk map gives all lanes of a wave chunks of one parity.
+
+constexpr int kRepBinomStride = kMaxN + 1;  // binom table row: C(m_k, 0..64)
+constexpr int kRepMaxLog2Chunk = 14;        // L <= 2^14
+
+struct RepMult {
+  int32_t m[kMaxN];
+};
+
+struct RepArgs {
+  const double* staged;   // [+C | 0] [-C | 0] (n x (R+1) each), then the two start columns
+  const double* binom;    // R x kRepBinomStride: C(m_k, f) as doubles
+  const double* tin;      // 2 x L: signed weight of the inner digits at step s (parity 0, 1)
+  const int32_t* toff;    // 2 x L: offset (doubles) into staged of the column added after
+                          // step s; the last step adds the zero column
+  const int32_t* radix;   // R radices m_k + 1
+  const int32_t* status;  // staging status; nonzero -> the walk does nothing
+  uint64_t first;         // first chunk (walk) or first Gray index (single terms)
+  uint64_t nchunks;
+  uint64_t ntasks;        // 2 * ceil(nchunks / 128)
+  int32_t R, b, L, pad;
+  void* partials;         // per workgroup: dd (real) or complex dd
+};
+
+hipError_t launch_rep_stage(int is_complex, const double* C, int n, int R, int ld,
+                            const RepMult& mult, int b, int L, int row_scaling, double* staged,
+                            double* binom, double* tin, int32_t* toff, int32_t* radix,
+                            int32_t* rowexp, int32_t* status, hipStream_t s);
+// single: every lane sums one term (Gray indices first .. first + nchunks - 1).
+hipError_t launch_rep_walk_real_lo(int n, bool single, const RepArgs& a, int grid, hipStream_t s);
+hipError_t launch_rep_walk_real_hi(int n, bool single, const RepArgs& a, int grid, hipStream_t s);
+hipError_t launch_rep_walk_complex_lo(int n, bool single, const RepArgs& a, int grid,
+                                      hipStream_t s);
+hipError_t launch_rep_walk_complex_hi(int n, bool single, const RepArgs& a, int grid,
+                                      hipStream_t s);
+
 // Rows per exactly-multiplied group in the 0/1 walk: the largest k with
 // n^k < 2^50 (|2 w_i| <= n, so a group's product stays below 2^50).
 constexpr int int01_group_rows(int n) {
