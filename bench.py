@@ -12,9 +12,10 @@ Printed: one JSON line with the throughput, the roofline of the walk kernel
 issue peak; the kernel's own duration comes from HIP events recorded by the
 library on the launch stream), and the CPU oracle timed on the host cores.
 
-Other workloads (--workload c1|c3|c5|c4) are for manual runs; c5 (48x48
+Other workloads (--workload c1|c3|c5|c4|c6) are for manual runs; c5 (48x48
 real, 2^47 terms, minutes per permanent) runs as 16 perm_partial slices with
-a progress line each.
+a progress line each; c6 is the repeated-column path (Eq. ryser2) on a
+48-photon output with two photons in each of 24 modes.
 """
 from __future__ import annotations
 
@@ -92,7 +93,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    p.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "c6"])
     p.add_argument("--count", type=int, default=100000, help="c4: number of matrices")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--blocks", type=int, default=0)
@@ -264,6 +265,68 @@ def bench_batched(args):
     print(json.dumps(outj))
 
 
+def bench_repeated(args):
+    """48 photons leaving a 2304-mode Haar interferometer two per output in 24
+    outputs: per of the 48 x 48 matrix with 24 distinct columns of
+    multiplicity 2, by Eq. ryser2 (3^24 terms instead of 2^47)."""
+    import numpy as np
+    import torch
+    from paper_1904_06229_amd import binding as B, inputs
+
+    n, R, seed = 48, 24, 20190406
+    U = inputs.haar_block(n, n * n, seed)
+    C = np.ascontiguousarray(U[:, :R])
+    mult = [2] * R
+    dC = torch.from_numpy(np.asfortranarray(C)).to("cuda")
+    T = 3 ** R
+    for _ in range(args.warmup):
+        r = B.perm_repeated(dC, mult, blocks=args.blocks, log2_chunk=args.log2_chunk)
+    torch.cuda.synchronize()
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = B.perm_repeated(dC, mult, blocks=args.blocks, log2_chunk=args.log2_chunk)
+        kms.append(r.kernel_ms)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kavg = sum(kms) / len(kms)
+    # per term: 2n row-sum updates, n-1 complex multiplies (4), weight (2), accumulate (2)
+    alg = 6.0 * n * T
+    out = {
+        "metric": "weighted Ryser terms/sec (n*prod(m_k+1)/s)",
+        "value": args.steps * n * float(T) / dt, "unit": "n*prod(m_k+1)/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"48x48 complex, 24 distinct columns x 2 (first 24 columns of "
+                               f"the 48 x 2304 Haar block, seed {seed}), Eq. ryser2",
+                   "n": n, "R": R, "terms": T, "inner_digits": r.log2_chunk, "blocks": r.blocks},
+        "roofline": {"bound": "alu", "achieved": alg / (kavg * 1e-3) / 1e12,
+                     "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
+                     "frac": alg / (kavg * 1e-3) / PEAK_LANE_OPS, "traffic": None,
+                     "kernel": f"rep_walk_kernel<{n}, false> (complex)", "kernel_ms": kavg,
+                     "ops_per_launch": alg},
+        "result": repr(complex(r.re_hi + r.re_lo, r.im_hi + r.im_lo)),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        threads = oracle.default_threads()
+        count = 1 << 12
+        while True:
+            t1 = time.perf_counter()
+            oracle.ryser2_range(C, mult, 0, count, threads=threads)
+            cdt = time.perf_counter() - t1
+            if cdt >= 5.0 or count >= T:
+                break
+            count = min(T, count * 2 ** max(1, min(8, int(math.log2(10.0 / max(cdt, 1e-4))))))
+        out["cpu_baseline"] = {"value": n * count / cdt, "unit": "n*prod(m_k+1)/s",
+                               "cores": threads, "kind": "oracle",
+                               "sample": f"first {count} of the {T} Gray terms, each formed "
+                                         "directly (long double)", "seconds": round(cdt, 3)}
+    print(json.dumps(out))
+
+
 def bench_sliced(args):
     """Each step is one whole permanent as consecutive perm_partial slices
     (a progress line per slice on stderr); slice sums are added in slice order."""
@@ -330,6 +393,8 @@ def main():
         sys.exit(2)
     if args.workload == "c4":
         return bench_batched(args)
+    if args.workload == "c6":
+        return bench_repeated(args)
     if args.slices or args.checkpoint or (args.workload == "c5" and not args.terms_log2):
         return bench_sliced(args)
     import numpy as np

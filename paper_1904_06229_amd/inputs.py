@@ -98,6 +98,44 @@ def batched_haar_blocks(count: int, n_lo: int, n_hi: int, seed: int, qr=None):
     return sizes, mats
 
 
+# ---- random-matrix ensembles (Secs. III-VI) ---------------------------------
+
+ENSEMBLES = ("gaussian", "circular", "bernoulli", "haar")
+
+
+def ensemble_batch(kind: str, n: int, count: int, seed: int, a: float = 2.0, qr=None):
+    """``count`` n x n matrices of one ensemble, as a (count, n, n) array.
+
+    gaussian  : Ginibre entries (g1 + i g2)/sqrt(2), mean 0, variance 1 (Sec. III)
+    circular  : exp(i theta), theta uniform on [0, 2 pi) (Sec. IV)
+    bernoulli : real +1 / -1 with probability 1/2 each (Sec. V)
+    haar      : S = sqrt(m) U_n, U_n the top-left block of an m x m Haar
+                unitary, m = round(n^a) (the family S(n^a, n) of Sec. VI)
+    Every entry has variance 1, so E |per|^2 = n! in each ensemble
+    (exactly for the first three).
+    """
+    r = rng(seed)
+    if kind == "gaussian":
+        g = r.standard_normal((count, n, n, 2))
+        return (g[..., 0] + 1j * g[..., 1]) / np.sqrt(2.0)
+    if kind == "circular":
+        return np.exp(1j * r.uniform(0.0, 2.0 * np.pi, size=(count, n, n)))
+    if kind == "bernoulli":
+        return np.where(r.random((count, n, n)) < 0.5, 1.0, -1.0)
+    if kind == "haar":
+        qr = qr or (lambda G: np.linalg.qr(G, mode="reduced"))
+        m = max(n, int(round(n ** a)))
+        out = np.empty((count, n, n), dtype=np.complex128)
+        for lo in range(0, count, 2048):
+            k = min(2048, count - lo)
+            g = r.standard_normal((k, m, n, 2))
+            Q, R = qr((g[..., 0] + 1j * g[..., 1]) / np.sqrt(2.0))
+            d = np.diagonal(R, axis1=1, axis2=2)
+            out[lo:lo + k] = np.sqrt(m) * (Q * (d / np.abs(d))[:, None, :])[:, :n, :]
+        return out
+    raise ValueError(f"unknown ensemble {kind!r}; one of {ENSEMBLES}")
+
+
 # ---- structured matrices with closed-form permanents -----------------------
 
 def ones(n: int) -> np.ndarray:
