@@ -20,6 +20,8 @@ arrays through ctypes.  Routes (see the C file for the passages they follow):
                        multiplicities; ``ryser2_range`` is its raw sum over a
                        range of the reflected mixed-radix Gray order, and
                        ``mixed_gray`` unranks that order.
+* ``band``          -- the band transfer matrix of App. C (bandpermanent) for
+                       matrices with a_ij = 0 when |i - j| > k.
 
 Real results come back as :class:`Pair` (an unevaluated double pair hi + lo
 holding the long-double value), complex ones as :class:`CPair`, integer ones
@@ -79,6 +81,8 @@ def _load():
         "oracle_default_threads": ([]),
         "oracle_ryser2": ([dp, i, i, i, ctypes.POINTER(ctypes.c_int), i, i, dp]),
         "oracle_ryser2_range": ([dp, i, i, i, ctypes.POINTER(ctypes.c_int), i, u64, u64, i, dp]),
+        "oracle_band_real": ([dp, i, i, i, i, dp]),
+        "oracle_band_int": ([bp, i, i, i, up]),
         "oracle_mixed_gray": ([u64, i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     }
     for name, args in sig.items():
@@ -264,6 +268,21 @@ def mixed_gray(g: int, radices):
     f = (ctypes.c_int * R)()
     _check(lib.oracle_mixed_gray(g, R, r, f), "mixed_gray")
     return [int(x) for x in f]
+
+
+def band(A, k: int):
+    """per(A) by the App. C transfer matrix; A must vanish outside |i - j| <= k (k <= 9)."""
+    lib = _load()
+    M, n, kind = _prep(A)
+    if kind == "int":
+        out = (ctypes.c_uint64 * 2)()
+        _check(lib.oracle_band_int(_ptr(M, kind), n, max(n, 1), k, out), "band")
+        return _words_to_int(out)
+    out = (ctypes.c_double * 4)()
+    _check(lib.oracle_band_real(_ptr(M, kind), n, max(n, 1), k, 1 if kind == "complex" else 0,
+                                out), "band")
+    return CPair(Pair(out[0], out[1]), Pair(out[2], out[3])) if kind == "complex" \
+        else Pair(out[0], out[1])
 
 
 def default_threads() -> int:

@@ -40,6 +40,13 @@
  *                          form runs over f in reflected mixed-radix Gray
  *                          order (the paper fixes no order for Eq. ryser2),
  *                          every term formed directly from f.
+ *   O6 oracle_band_*       The band transfer matrix of App. C (bandpermanent)
+ *                          for a_ij = 0 when |i-j| > k: the product of the
+ *                          row forms C_i = sum_j a_ij x_j, kept as a
+ *                          polynomial in the column variables with
+ *                          x_j^2 = 0, the variable of the column that leaves
+ *                          the band set to 1 after each row, and all of
+ *                          them set to 1 at the end.
  *
  * Threads (pthreads) only split index ranges evenly (App. A, distribute);
  * every thread's partial result lands in an array that is added in index
@@ -862,6 +869,120 @@ int oracle_mixed_gray(uint64_t g, int R, const int* radix, int* f) {
   }
   if ((u128)g >= t) return -1;
   mixed_gray_unrank(g, R, Q, f);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O6: band transfer matrix (App. C, bandpermanent)                          */
+/* ------------------------------------------------------------------------ */
+
+/* The polynomial is stored by its monomials: a monomial is a set of column
+ * variables, all from the window of columns [base, base + 2k + 1] that can
+ * still be unset (columns below base have been set to 1, columns above the
+ * window cannot have appeared yet).  Bit b of a mask stands for column
+ * base + b.  Before row i (0-based) base = i - k - 1. */
+#define ORACLE_BAND_MAX_K 9
+
+static int band_args_ok(int n, int ld, int k) {
+  return n >= 1 && n <= 4096 && ld >= n && k >= 0 && k <= ORACLE_BAND_MAX_K;
+}
+
+/* Out-of-band entries must be zero (the algorithm never reads them). */
+static int band_zero_outside_real(const double* A, int n, int ld, int k, int cw) {
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i)
+      if (i - j > k || j - i > k)
+        for (int c = 0; c < cw; ++c)
+          if (A[cw * (i + (size_t)j * ld) + c] != 0.0) return 0;
+  return 1;
+}
+
+int oracle_band_real(const double* A, int n, int ld, int k, int cplx, double* out) {
+  if (!band_args_ok(n, ld, k)) return -1;
+  const int cw = cplx ? 2 : 1;
+  if (!band_zero_outside_real(A, n, ld, k, cw)) return -1;
+  const int W = 2 * k + 2; /* window bits before the shift */
+  const size_t S = (size_t)1 << W;
+  long double* re = calloc(S, sizeof(long double));
+  long double* im = calloc(S, sizeof(long double));
+  long double* nre = calloc(S, sizeof(long double));
+  long double* nim = calloc(S, sizeof(long double));
+  if (!re || !im || !nre || !nim) {
+    free(re); free(im); free(nre); free(nim);
+    return -2;
+  }
+  re[0] = 1.0L; /* p := 1 */
+  for (int i = 0; i < n; ++i) {
+    const int base = i - k - 1;
+    /* p := p * C_i, dropping monomials with a squared variable */
+    memset(nre, 0, S * sizeof(long double));
+    memset(nim, 0, S * sizeof(long double));
+    for (size_t m = 0; m < S; ++m) {
+      if (re[m] == 0.0L && im[m] == 0.0L) continue;
+      for (int j = (i - k > 0 ? i - k : 0); j <= i + k && j < n; ++j) {
+        const int b = j - base;
+        if ((m >> b) & 1) continue; /* x_j^2 = 0 */
+        const size_t o = cw * (i + (size_t)j * ld);
+        const long double ar = (long double)A[o];
+        const long double ai = cplx ? (long double)A[o + 1] : 0.0L;
+        nre[m | ((size_t)1 << b)] += re[m] * ar - im[m] * ai;
+        nim[m | ((size_t)1 << b)] += re[m] * ai + im[m] * ar;
+      }
+    }
+    /* set x_{base} = 1 (column i-k-1 leaves the band): merge bit 0 away and
+     * move the window up by one column */
+    memset(re, 0, S * sizeof(long double));
+    memset(im, 0, S * sizeof(long double));
+    for (size_t m = 0; m < S; ++m) {
+      re[m >> 1] += nre[m];
+      im[m >> 1] += nim[m];
+    }
+  }
+  /* set every remaining x_j = 1 */
+  kahan_ld Sr = {0.0L, 0.0L}, Si = {0.0L, 0.0L};
+  for (size_t m = 0; m < S; ++m) {
+    kahan_add(&Sr, re[m]);
+    kahan_add(&Si, im[m]);
+  }
+  ld_to_pair(Sr.s, out);
+  ld_to_pair(Si.s, out + 2);
+  free(re); free(im); free(nre); free(nim);
+  return 0;
+}
+
+/* 0/1 band matrices, exact modulo 2^128. */
+int oracle_band_int(const uint8_t* B, int n, int ld, int k, uint64_t* out) {
+  if (!band_args_ok(n, ld, k)) return -1;
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i)
+      if ((i - j > k || j - i > k) && B[i + (size_t)j * ld] != 0) return -1;
+  const int W = 2 * k + 2;
+  const size_t S = (size_t)1 << W;
+  u128* c = calloc(S, sizeof(u128));
+  u128* nc = calloc(S, sizeof(u128));
+  if (!c || !nc) {
+    free(c); free(nc);
+    return -2;
+  }
+  c[0] = 1;
+  for (int i = 0; i < n; ++i) {
+    const int base = i - k - 1;
+    memset(nc, 0, S * sizeof(u128));
+    for (size_t m = 0; m < S; ++m) {
+      if (c[m] == 0) continue;
+      for (int j = (i - k > 0 ? i - k : 0); j <= i + k && j < n; ++j) {
+        const int b = j - base;
+        if ((m >> b) & 1) continue;
+        if (B[i + (size_t)j * ld]) nc[m | ((size_t)1 << b)] += c[m] * (u128)B[i + (size_t)j * ld];
+      }
+    }
+    memset(c, 0, S * sizeof(u128));
+    for (size_t m = 0; m < S; ++m) c[m >> 1] += nc[m];
+  }
+  u128 sum = 0;
+  for (size_t m = 0; m < S; ++m) sum += c[m];
+  u128_to_pair(sum, out);
+  free(c); free(nc);
   return 0;
 }
 
