@@ -15,7 +15,8 @@ library on the launch stream), and the CPU oracle timed on the host cores.
 Other workloads (--workload c1|c3|c5|c4|c6) are for manual runs; c5 (48x48
 real, 2^47 terms, minutes per permanent) runs as 16 perm_partial slices with
 a progress line each; c6 is the repeated-column path (Eq. ryser2) on a
-48-photon output with two photons in each of 24 modes.
+48-photon output with two photons in each of 24 modes; c7 is the band
+transfer matrix (App. C) on a batch of 64 x 64 band matrices.
 """
 from __future__ import annotations
 
@@ -93,7 +94,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "c6"])
+    p.add_argument("--workload", default="c2",
+                   choices=["c1", "c2", "c3", "c4", "c5", "c6", "c7"])
     p.add_argument("--count", type=int, default=100000, help="c4: number of matrices")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--blocks", type=int, default=0)
@@ -327,6 +329,90 @@ def bench_repeated(args):
     print(json.dumps(out))
 
 
+# LDS: 128 bytes per clock per CU (gfx950), 256 CUs, 2.4 GHz.
+PEAK_LDS_BYTES = 256 * 128 * 2.4e9
+
+
+def band_macs_per_row(k: int) -> int:
+    """Multiply-adds of one interior row of the App. C transfer matrix: for every
+    coefficient mask M after the row and both states of the column that leaves
+    the band, one product per band column present in Q = 2M + b0 (only column
+    i+k when Q holds it)."""
+    top = 2 * k + 1
+    total = 0
+    for t in range(1 << top):
+        for b0 in (0, 1):
+            q = (t << 1) | b0
+            total += 1 if (q >> top) & 1 else bin(q & (((1 << top) - 1) & ~1)).count("1")
+    return total
+
+
+def bench_band(args):
+    """20000 complex 64 x 64 band matrices (a_ij = 0 for |i - j| > 5), Gaussian
+    entries, by the App. C transfer matrix (perm_band)."""
+    import numpy as np
+    import torch
+    from paper_1904_06229_amd import binding as B
+
+    n, k, count, seed = 64, 5, args.count if args.count != 100000 else 20000, 20190407
+    r = np.random.default_rng(seed)
+    i = np.arange(n)
+    mask = np.abs(i[:, None] - i[None, :]) <= k
+    mats = np.where(mask, r.standard_normal((count, n, n)) + 1j * r.standard_normal((count, n, n)),
+                    0) / math.sqrt(2.0)
+    flat = np.ascontiguousarray(np.transpose(mats, (0, 2, 1))).ravel().view(np.float64)
+    dA = torch.from_numpy(flat).to("cuda")
+    offs = [m * 2 * n * n for m in range(count)]
+    out = torch.zeros(4 * count, dtype=torch.float64, device="cuda")
+    st = torch.zeros(count, dtype=torch.int32, device="cuda")
+    for _ in range(args.warmup):
+        B.perm_band(dA, [n] * count, offs, k, True, out, st, blocks=args.blocks)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ev0.record()
+        B.perm_band(dA, [n] * count, offs, k, True, out, st, blocks=args.blocks)
+        ev1.record()
+        ev1.synchronize()
+        kms.append(ev0.elapsed_time(ev1))
+    dt = time.perf_counter() - t0
+    assert int((st != 0).sum()) == 0
+    kavg = sum(kms) / len(kms)
+    macs = band_macs_per_row(k) * n * count  # interior-row count (edge rows do less)
+    lds_bytes = 16.0 * macs                    # one complex coefficient read per multiply-add
+    res = out.view(-1, 4)[0].cpu().numpy()
+    o = {
+        "metric": "band permanents/s (App. C transfer matrix)",
+        "value": args.steps * count / dt, "unit": "permanents/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{count} complex 64x64 band matrices, k = 5, Ginibre entries on "
+                               f"the band, seed {seed}", "n": n, "k": k, "count": count},
+        "roofline": {"bound": "lds", "achieved": lds_bytes / (kavg * 1e-3) / 1e9,
+                     "peak": PEAK_LDS_BYTES / 1e9, "unit": "GB/s",
+                     "frac": lds_bytes / (kavg * 1e-3) / PEAK_LDS_BYTES, "traffic": None,
+                     "kernel": "band_kernel<5, true>", "kernel_ms": kavg,
+                     "macs_per_launch": macs},
+        "result_first": repr(complex(res[0] + res[1], res[2] + res[3])),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        t1 = time.perf_counter()
+        done = 0
+        while time.perf_counter() - t1 < 10.0 and done < count:
+            oracle.band(mats[done], k)
+            done += 1
+        cdt = time.perf_counter() - t1
+        o["cpu_baseline"] = {"value": done / cdt, "unit": "permanents/s", "cores": 1,
+                             "kind": "oracle", "sample": f"first {done} matrices of the batch, "
+                             "long-double transfer matrix, one thread", "seconds": round(cdt, 2)}
+    print(json.dumps(o))
+
+
 def bench_sliced(args):
     """Each step is one whole permanent as consecutive perm_partial slices
     (a progress line per slice on stderr); slice sums are added in slice order."""
@@ -395,6 +481,8 @@ def main():
         return bench_batched(args)
     if args.workload == "c6":
         return bench_repeated(args)
+    if args.workload == "c7":
+        return bench_band(args)
     if args.slices or args.checkpoint or (args.workload == "c5" and not args.terms_log2):
         return bench_sliced(args)
     import numpy as np

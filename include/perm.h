@@ -219,6 +219,32 @@ perm_status perm_repeated_partial(int dtype, const double* dC, int n, int R, int
                                   const int32_t* mult, uint64_t start, uint64_t count,
                                   const perm_opts* opts, perm_result* out, void* stream);
 
+/*
+ * perm_band -- permanents of band matrices (a_ij = 0 whenever |i - j| > k) by
+ * the transfer matrix of App. C (bandpermanent), one workgroup per matrix.
+ *   per(A) is the sum of the coefficients of prod_i (sum_j a_ij x_j) with every
+ *   x_j^2 = 0; after row i the variable of column i-k-1 is set to 1, so only
+ *   the 2^(2k+1) monomials over columns i-k..i+k are kept.  n * 2^(2k+1) * O(k)
+ *   operations per matrix, no inclusion-exclusion and so no cancellation beyond
+ *   that of the entries themselves.
+ *   dtype    PERM_DT_REAL or PERM_DT_COMPLEX.
+ *   dA       device array, matrices back to back; matrix m starts at element offset
+ *            h_offset[m] (in doubles) and is column-major with ld = n_m (complex:
+ *            interleaved pairs).  Entries with |i - j| > k are not read: the result is
+ *            the permanent of the band part.
+ *   h_n      HOST array of sizes, 1 <= n_m <= 65536; h_offset HOST array of offsets.
+ *   k        0 <= k <= 5 (the coefficients live in LDS).
+ *   d_out    device array, 4 doubles per matrix: re_hi, re_lo, im_hi, im_lo (each row is
+ *            scaled by a power of two during the product and the scale is restored at the
+ *            end; values beyond the double range come back as +-inf).
+ *   d_status device array of count int32 (may be NULL): PERM_OK or PERM_ENONFINITE.
+ * Options: only `blocks` (workgroups; 0 = 8 per CU).  Waits for `stream`.
+ * Errors: PERM_EINVAL, PERM_ENOTIMPL (other options), PERM_ENOMEM, PERM_EHIP.
+ */
+perm_status perm_band(int dtype, const double* dA, const int32_t* h_n, const int64_t* h_offset,
+                      int count, int k, const perm_opts* opts, double* d_out, int32_t* d_status,
+                      void* stream);
+
 /* Chunk plan for a Gray-index range, computed on the host (no GPU needed). */
 typedef struct {
   int32_t log2_chunk;      /* L = 2^log2_chunk */

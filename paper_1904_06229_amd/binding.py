@@ -56,6 +56,7 @@ SIGNATURES = {
     "perm_partial": ([_i, _vp, _i, _i, _u64, _u64, ctypes.POINTER(perm_opts),
                       ctypes.POINTER(perm_result), _vp], _i),
     "perm_batched": ([_vp, _vp, _vp, _i, _i, ctypes.POINTER(perm_opts), _vp, _vp, _vp], _i),
+    "perm_band": ([_i, _vp, _vp, _vp, _i, _i, ctypes.POINTER(perm_opts), _vp, _vp, _vp], _i),
     "perm_repeated": ([_i, _vp, _i, _i, _i, ctypes.POINTER(ctypes.c_int32),
                        ctypes.POINTER(perm_opts), ctypes.POINTER(perm_result), _vp], _i),
     "perm_repeated_partial": ([_i, _vp, _i, _i, _i, ctypes.POINTER(ctypes.c_int32), _u64, _u64,
@@ -268,6 +269,25 @@ def perm_repeated_partial(C, mult, start: int, count: int, stream=None, **opts) 
                                       ctypes.byref(r), _stream_handle(stream)),
            "perm_repeated_partial")
     return _result(r, False)
+
+
+def perm_band(A_packed, sizes, offsets, k: int, is_complex: bool, out, status=None, stream=None,
+              **opts) -> None:
+    """Band permanents (App. C) of the matrices packed in ``A_packed``; results in ``out``."""
+    import torch
+    count = len(sizes)
+    n_arr = (ctypes.c_int32 * max(count, 1))(*[int(x) for x in sizes])
+    o_arr = (ctypes.c_int64 * max(count, 1))(*[int(x) for x in offsets])
+    o = make_opts(**opts)
+    if A_packed.dtype != torch.float64 or out.dtype != torch.float64:
+        raise TypeError("A_packed and out must be float64 (complex data as interleaved pairs)")
+    if out.numel() < 4 * count:
+        raise ValueError("out needs 4 doubles per matrix")
+    st_ptr = ctypes.c_void_p(status.data_ptr()) if status is not None else ctypes.c_void_p(0)
+    dt = PERM_DT_COMPLEX if is_complex else PERM_DT_REAL
+    _check(_lib.perm_band(dt, ctypes.c_void_p(A_packed.data_ptr()), n_arr, o_arr, count, int(k),
+                          ctypes.byref(o), ctypes.c_void_p(out.data_ptr()), st_ptr,
+                          _stream_handle(stream)), "perm_band")
 
 
 def perm_batched(A_packed, sizes, offsets, is_complex: bool, out, status=None, stream=None,

@@ -34,11 +34,13 @@ SOURCES = [
     ("kern_repeated.hip", ["-DPERM_CPLX=1", "-DPERM_HALF=0"]),
     ("kern_repeated.hip", ["-DPERM_CPLX=1", "-DPERM_HALF=1"]),
     ("kern_repeated_stage.hip", []),
+    ("kern_band.hip", []),
     ("kern_stage.hip", []),
     ("kern_batched.hip", []),
     ("perm_host.cpp", []),
     ("perm_batched.cpp", []),
     ("perm_repeated.cpp", []),
+    ("perm_band.cpp", []),
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

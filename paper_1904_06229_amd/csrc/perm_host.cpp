@@ -500,6 +500,7 @@ void perm_release(void) {
   g_ws.clear();
   perm::batched_release();
   perm::repeated_release();
+  perm::band_release();
   (void)hipSetDevice(cur);
 }
 

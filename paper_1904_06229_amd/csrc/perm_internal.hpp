@@ -162,6 +162,22 @@ hipError_t launch_rep_walk_complex_lo(int n, bool single, const RepArgs& a, int 
 hipError_t launch_rep_walk_complex_hi(int n, bool single, const RepArgs& a, int grid,
                                       hipStream_t s);
 
+// ------------------------------------------------------------------ band ----
+// App. C transfer matrix (perm_band): one workgroup per matrix.
+constexpr int kBandMaxK = 5;  // 2^(2k+1) coefficients in LDS, double-buffered
+
+struct BandArgs {
+  const double* A;        // matrices back to back (column-major, ld = n; complex pairs)
+  const int64_t* off;     // element offset (doubles) of matrix m
+  const int32_t* n;       // sizes
+  int32_t count;
+  int32_t pad;
+  double* out;            // 4 doubles per matrix
+  int32_t* status;        // per matrix (may be null)
+};
+
+hipError_t launch_band(bool cplx, int k, const BandArgs& a, int grid, hipStream_t s);
+
 // Rows per exactly-multiplied group in the 0/1 walk: the largest k with
 // n^k < 2^50 (|2 w_i| <= n, so a group's product stays below 2^50).
 constexpr int int01_group_rows(int n) {
