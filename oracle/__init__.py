@@ -20,6 +20,11 @@ arrays through ctypes.  Routes (see the C file for the passages they follow):
                        multiplicities; ``ryser2_range`` is its raw sum over a
                        range of the reflected mixed-radix Gray order, and
                        ``mixed_gray`` unranks that order.
+* ``sparse``        -- App. B: greedypartition, then Eq. ryser over the column
+                       sets that meet every block (``sparse_range``: raw sum
+                       over a range of its mixed-radix Gray order;
+                       ``sparse_partition`` / ``sparse_set`` expose the
+                       partition and the set of a Gray index).
 * ``band``          -- the band transfer matrix of App. C (bandpermanent) for
                        matrices with a_ij = 0 when |i - j| > k.
 
@@ -81,6 +86,11 @@ def _load():
         "oracle_default_threads": ([]),
         "oracle_ryser2": ([dp, i, i, i, ctypes.POINTER(ctypes.c_int), i, i, dp]),
         "oracle_ryser2_range": ([dp, i, i, i, ctypes.POINTER(ctypes.c_int), i, u64, u64, i, dp]),
+        "oracle_sparse_real": ([dp, i, i, i, i, dp, up]),
+        "oracle_sparse_int": ([bp, i, i, i, up, up]),
+        "oracle_sparse_range": ([dp, i, i, i, u64, u64, i, dp]),
+        "oracle_sparse_partition": ([dp, i, i, i, ctypes.POINTER(ctypes.c_int)]),
+        "oracle_sparse_set": ([dp, i, i, i, u64, up]),
         "oracle_band_real": ([dp, i, i, i, i, dp]),
         "oracle_band_int": ([bp, i, i, i, up]),
         "oracle_mixed_gray": ([u64, i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
@@ -268,6 +278,64 @@ def mixed_gray(g: int, radices):
     f = (ctypes.c_int * R)()
     _check(lib.oracle_mixed_gray(g, R, r, f), "mixed_gray")
     return [int(x) for x in f]
+
+
+def _prep_float(A):
+    M, n, kind = _prep(A)
+    if kind == "int":
+        M = np.asfortranarray(M, dtype=np.float64)
+        kind = "real"
+    return M, n, 1 if kind == "complex" else 0
+
+
+def sparse(A, threads: int = 0):
+    """(per(A), number of column sets enumerated) by App. B's sparse Ryser sum."""
+    lib = _load()
+    M, n, kind = _prep(A)
+    terms = ctypes.c_uint64()
+    if kind == "int":
+        out = (ctypes.c_uint64 * 2)()
+        _check(lib.oracle_sparse_int(_ptr(M, kind), n, max(n, 1), threads, out,
+                                     ctypes.byref(terms)), "sparse")
+        return _words_to_int(out), terms.value
+    out = (ctypes.c_double * 4)()
+    cplx = 1 if kind == "complex" else 0
+    _check(lib.oracle_sparse_real(_ptr(M, kind), n, max(n, 1), cplx, threads, out,
+                                  ctypes.byref(terms)), "sparse")
+    val = CPair(Pair(out[0], out[1]), Pair(out[2], out[3])) if cplx else Pair(out[0], out[1])
+    return val, terms.value
+
+
+def sparse_range(A, g0: int, count: int, threads: int = 0):
+    """Raw App. B sum (no (-1)^n) over Gray indices [g0, g0+count) of its digit order."""
+    lib = _load()
+    M, n, cplx = _prep_float(A)
+    out = (ctypes.c_double * 4)()
+    _check(lib.oracle_sparse_range(M.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n,
+                                   max(n, 1), cplx, g0, count, threads, out), "sparse_range")
+    return CPair(Pair(out[0], out[1]), Pair(out[2], out[3])) if cplx else Pair(out[0], out[1])
+
+
+def sparse_partition(A):
+    """Block index of every column (selection order), -1 for the columns of T."""
+    lib = _load()
+    M, n, cplx = _prep_float(A)
+    blk = (ctypes.c_int * n)()
+    nb = lib.oracle_sparse_partition(M.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n,
+                                     max(n, 1), cplx, blk)
+    if nb < 0:
+        raise ValueError("oracle sparse_partition: invalid arguments or a zero row")
+    return [int(x) for x in blk]
+
+
+def sparse_set(A, g: int) -> int:
+    """Column set (bit mask) of Gray index g of the App. B enumeration."""
+    lib = _load()
+    M, n, cplx = _prep_float(A)
+    J = ctypes.c_uint64()
+    _check(lib.oracle_sparse_set(M.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n, max(n, 1),
+                                 cplx, g, ctypes.byref(J)), "sparse_set")
+    return J.value
 
 
 def band(A, k: int):

@@ -40,6 +40,12 @@
  *                          form runs over f in reflected mixed-radix Gray
  *                          order (the paper fixes no order for Eq. ryser2),
  *                          every term formed directly from f.
+ *   O7 oracle_sparse_*     The sparse form of Ryser's formula (App. B):
+ *                          greedypartition picks rows of least degree with
+ *                          pairwise disjoint column sets S_1..S_d; the sum of
+ *                          Eq. ryser runs only over column sets J that meet
+ *                          every S_l (a nonempty subset of each S_l times any
+ *                          subset of the rest T), which drops only zero terms.
  *   O6 oracle_band_*       The band transfer matrix of App. C (bandpermanent)
  *                          for a_ij = 0 when |i-j| > k: the product of the
  *                          row forms C_i = sum_j a_ij x_j, kept as a
@@ -983,6 +989,312 @@ int oracle_band_int(const uint8_t* B, int n, int ld, int k, uint64_t* out) {
   for (size_t m = 0; m < S; ++m) sum += c[m];
   u128_to_pair(sum, out);
   free(c); free(nc);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O7: sparse matrices (App. B, greedypartition and sparsepermanent)         */
+/* ------------------------------------------------------------------------ */
+
+/* Blocks larger than this do not restrict the sum (their columns join T):
+ * the enumeration of a block's nonempty subsets is kept to 2^12 - 1 values.
+ * Dropping a restriction only adds zero terms. */
+#define ORACLE_SPARSE_MAX_BLOCK 12
+
+typedef struct {
+  int nblocks;
+  int block_first[ORACLE_MAX_N]; /* index into cols[] of block l's first column */
+  int block_size[ORACLE_MAX_N];
+  int ntail;                     /* |T| */
+  int cols[ORACLE_MAX_N];        /* blocks in selection order (columns ascending
+                                    inside), then the columns of T ascending */
+} sparse_part;
+
+static int entry_nonzero(const double* A, const uint8_t* B, int ld, int cplx, int i, int j) {
+  if (B) return B[i + (size_t)j * ld] != 0;
+  if (cplx) return A[2 * (i + (size_t)j * ld)] != 0.0 || A[2 * (i + (size_t)j * ld) + 1] != 0.0;
+  return A[i + (size_t)j * ld] != 0.0;
+}
+
+/* greedypartition (App. B): repeatedly take the remaining row k of least
+ * degree (the lowest index among equals), make its column set N_k a block,
+ * and drop row k and every remaining row whose column set meets N_k.  The
+ * blocks are pairwise disjoint; T is the set of columns in no block. */
+static int greedy_partition(const double* A, const uint8_t* B, int n, int ld, int cplx,
+                            sparse_part* P) {
+  int deg[ORACLE_MAX_N], alive[ORACLE_MAX_N];
+  uint64_t nb[ORACLE_MAX_N];
+  for (int i = 0; i < n; ++i) {
+    nb[i] = 0;
+    for (int j = 0; j < n; ++j)
+      if (entry_nonzero(A, B, ld, cplx, i, j)) nb[i] |= 1ull << j;
+    deg[i] = popcount64(nb[i]);
+    if (deg[i] == 0) return 0; /* a zero row: per = 0, no partition */
+    alive[i] = 1;
+  }
+  uint64_t used = 0;
+  int nblocks = 0, ncols = 0;
+  for (;;) {
+    int k = -1;
+    for (int i = 0; i < n; ++i)
+      if (alive[i] && (k < 0 || deg[i] < deg[k])) k = i;
+    if (k < 0) break;
+    alive[k] = 0;
+    for (int l = 0; l < n; ++l)
+      if (alive[l] && (nb[l] & nb[k])) alive[l] = 0;
+    if (deg[k] > ORACLE_SPARSE_MAX_BLOCK) continue; /* too large to restrict */
+    P->block_first[nblocks] = ncols;
+    P->block_size[nblocks] = deg[k];
+    for (int j = 0; j < n; ++j)
+      if ((nb[k] >> j) & 1) P->cols[ncols++] = j;
+    used |= nb[k];
+    ++nblocks;
+  }
+  P->nblocks = nblocks;
+  P->ntail = 0;
+  for (int j = 0; j < n; ++j)
+    if (!((used >> j) & 1)) {
+      P->cols[ncols++] = j;
+      P->ntail++;
+    }
+  return 1;
+}
+
+/* Digits of the enumeration: one per block (radix 2^s - 1, value v standing
+ * for the nonempty subset gray(v + 1) of the block's columns), then one per
+ * column of T (radix 2: out or in). */
+static int sparse_radices(const sparse_part* P, uint64_t* radix, int* R) {
+  int r = 0;
+  for (int l = 0; l < P->nblocks; ++l) radix[r++] = (1ull << P->block_size[l]) - 1;
+  for (int t = 0; t < P->ntail; ++t) radix[r++] = 2;
+  *R = r;
+  return r;
+}
+
+/* Column set J (bit mask over columns) of digit vector f. */
+static uint64_t sparse_set(const sparse_part* P, const int* f) {
+  uint64_t J = 0;
+  int d = 0;
+  for (int l = 0; l < P->nblocks; ++l, ++d) {
+    const uint64_t sub = gray((uint64_t)f[d] + 1);
+    for (int e = 0; e < P->block_size[l]; ++e)
+      if ((sub >> e) & 1) J |= 1ull << P->cols[P->block_first[l] + e];
+  }
+  const int t0 = P->nblocks ? P->block_first[P->nblocks - 1] + P->block_size[P->nblocks - 1] : 0;
+  for (int t = 0; t < P->ntail; ++t, ++d)
+    if (f[d]) J |= 1ull << P->cols[t0 + t];
+  return J;
+}
+
+typedef struct {
+  const double* A;
+  const uint8_t* B;
+  const sparse_part* P;
+  const uint64_t* Q;
+  int n, ld, cplx, R, gray_order;
+  uint64_t g0, len;
+  long double re, im;
+  u128 acc;
+} sparse_job;
+
+static void* sparse_worker(void* arg) {
+  sparse_job* jb = (sparse_job*)arg;
+  const int n = jb->n, ld = jb->ld;
+  int f[ORACLE_MAX_N];
+  uint64_t radix[ORACLE_MAX_N];
+  int R;
+  sparse_radices(jb->P, radix, &R);
+  kahan_ld Sr = {0.0L, 0.0L}, Si = {0.0L, 0.0L};
+  u128 acc = 0;
+  for (uint64_t g = jb->g0; g < jb->g0 + jb->len; ++g) {
+    if (jb->gray_order) {
+      mixed_gray_unrank(g, R, jb->Q, f);
+    } else {
+      uint64_t q = g;
+      for (int d = 0; d < R; ++d) {
+        f[d] = (int)(q % radix[d]);
+        q /= radix[d];
+      }
+    }
+    const uint64_t J = sparse_set(jb->P, f);
+    const int odd = popcount64(J) & 1;
+    if (jb->B) {
+      u128 p = 1;
+      for (int i = 0; i < n; ++i) {
+        int64_t r = 0;
+        for (int j = 0; j < n; ++j)
+          if ((J >> j) & 1) r += jb->B[i + (size_t)j * ld];
+        p *= (u128)r;
+      }
+      acc = odd ? acc - p : acc + p;
+    } else {
+      long double pr = 1.0L, pi = 0.0L;
+      for (int i = 0; i < n; ++i) {
+        long double sr = 0.0L, si = 0.0L;
+        for (int j = 0; j < n; ++j)
+          if ((J >> j) & 1) {
+            if (jb->cplx) {
+              sr += (long double)jb->A[2 * (i + (size_t)j * ld)];
+              si += (long double)jb->A[2 * (i + (size_t)j * ld) + 1];
+            } else {
+              sr += (long double)jb->A[i + (size_t)j * ld];
+            }
+          }
+        long double nr = pr * sr - pi * si;
+        long double ni = pr * si + pi * sr;
+        pr = nr;
+        pi = ni;
+      }
+      kahan_add(&Sr, odd ? -pr : pr);
+      kahan_add(&Si, odd ? -pi : pi);
+    }
+  }
+  jb->re = Sr.s;
+  jb->im = Si.s;
+  jb->acc = acc;
+  return NULL;
+}
+
+/* Runs the enumeration over [g0, g0 + count) (counting or Gray order);
+ * returns -1 on bad arguments, 1 when a row is zero (per = 0), 0 otherwise. */
+static int sparse_run(const double* A, const uint8_t* B, int n, int ld, int cplx, int gray_order,
+                      uint64_t g0, int64_t count, int nthreads, long double* re, long double* im,
+                      u128* acc, uint64_t* total) {
+  if (n < 1 || n > ORACLE_MAX_N || ld < n) return -1;
+  sparse_part P;
+  memset(&P, 0, sizeof P);
+  if (!greedy_partition(A, B, n, ld, cplx, &P)) {
+    *re = *im = 0.0L;
+    *acc = 0;
+    *total = 0;
+    return 1;
+  }
+  uint64_t radix[ORACLE_MAX_N], Q[ORACLE_MAX_N];
+  int R;
+  sparse_radices(&P, radix, &R);
+  u128 t = 1;
+  for (int d = 0; d < R; ++d) {
+    Q[d] = (uint64_t)t;
+    t *= radix[d];
+    if (t > ((u128)1 << 63)) return -1;
+  }
+  *total = (uint64_t)t;
+  if (count < 0) count = (int64_t)t; /* whole sum */
+  if (g0 > (uint64_t)t || (uint64_t)count > (uint64_t)t - g0) return -1;
+  sparse_job jobs[ORACLE_MAX_THREADS];
+  pthread_t th[ORACLE_MAX_THREADS];
+  int T = pick_threads(nthreads, (uint64_t)count);
+  for (int k = 0; k < T; ++k) {
+    memset(&jobs[k], 0, sizeof jobs[k]);
+    jobs[k].A = A;
+    jobs[k].B = B;
+    jobs[k].P = &P;
+    jobs[k].Q = Q;
+    jobs[k].n = n;
+    jobs[k].ld = ld;
+    jobs[k].cplx = cplx;
+    jobs[k].R = R;
+    jobs[k].gray_order = gray_order;
+    uint64_t off, len;
+    distribute((uint64_t)count, (uint64_t)T, (uint64_t)k, &off, &len);
+    jobs[k].g0 = g0 + off;
+    jobs[k].len = len;
+  }
+  int started = 0;
+  for (int k = 0; k < T; ++k) {
+    if (pthread_create(&th[k], NULL, sparse_worker, &jobs[k]) != 0) break;
+    ++started;
+  }
+  for (int k = started; k < T; ++k) sparse_worker(&jobs[k]);
+  for (int k = 0; k < started; ++k) pthread_join(th[k], NULL);
+  kahan_ld Sr = {0.0L, 0.0L}, Si = {0.0L, 0.0L};
+  u128 a = 0;
+  for (int k = 0; k < T; ++k) {
+    kahan_add(&Sr, jobs[k].re);
+    kahan_add(&Si, jobs[k].im);
+    a += jobs[k].acc;
+  }
+  *re = Sr.s;
+  *im = Si.s;
+  *acc = a;
+  return 0;
+}
+
+/* per(A) (sparsepermanent): out [re hi, re lo, im hi, im lo]; terms = the
+ * number of column sets enumerated (0 when a row is zero). */
+int oracle_sparse_real(const double* A, int n, int ld, int cplx, int nthreads, double* out,
+                       uint64_t* terms) {
+  long double re, im;
+  u128 acc;
+  int rc = sparse_run(A, NULL, n, ld, cplx, 0, 0, -1, nthreads, &re, &im, &acc, terms);
+  if (rc < 0) return -1;
+  if (n & 1) {
+    re = -re;
+    im = -im;
+  }
+  ld_to_pair(re, out);
+  ld_to_pair(im, out + 2);
+  return 0;
+}
+
+int oracle_sparse_int(const uint8_t* B, int n, int ld, int nthreads, uint64_t* out,
+                      uint64_t* terms) {
+  long double re, im;
+  u128 acc;
+  int rc = sparse_run(NULL, B, n, ld, 0, 0, 0, -1, nthreads, &re, &im, &acc, terms);
+  if (rc < 0) return -1;
+  if (n & 1) acc = (u128)0 - acc;
+  u128_to_pair(acc, out);
+  return 0;
+}
+
+/* Raw sum (no (-1)^n) over Gray indices [g0, g0 + count) of the mixed-radix
+ * order of the digits above. */
+int oracle_sparse_range(const double* A, int n, int ld, int cplx, uint64_t g0, uint64_t count,
+                        int nthreads, double* out) {
+  long double re, im;
+  u128 acc;
+  uint64_t total;
+  if (count > (uint64_t)INT64_MAX) return -1;
+  int rc = sparse_run(A, NULL, n, ld, cplx, 1, g0, (int64_t)count, nthreads, &re, &im, &acc,
+                      &total);
+  if (rc != 0) return -1;
+  ld_to_pair(re, out);
+  ld_to_pair(im, out + 2);
+  return 0;
+}
+
+/* The partition: block_of_col[j] = block index (selection order) or -1 for
+ * T; returns the number of blocks, or -1 (bad arguments / a zero row). */
+int oracle_sparse_partition(const double* A, int n, int ld, int cplx, int* block_of_col) {
+  if (n < 1 || n > ORACLE_MAX_N || ld < n) return -1;
+  sparse_part P;
+  memset(&P, 0, sizeof P);
+  if (!greedy_partition(A, NULL, n, ld, cplx, &P)) return -1;
+  for (int j = 0; j < n; ++j) block_of_col[j] = -1;
+  for (int l = 0; l < P.nblocks; ++l)
+    for (int e = 0; e < P.block_size[l]; ++e) block_of_col[P.cols[P.block_first[l] + e]] = l;
+  return P.nblocks;
+}
+
+/* Column set (bit mask) of Gray index g, for tests of the order. */
+int oracle_sparse_set(const double* A, int n, int ld, int cplx, uint64_t g, uint64_t* J) {
+  if (n < 1 || n > ORACLE_MAX_N || ld < n) return -1;
+  sparse_part P;
+  memset(&P, 0, sizeof P);
+  if (!greedy_partition(A, NULL, n, ld, cplx, &P)) return -1;
+  uint64_t radix[ORACLE_MAX_N], Q[ORACLE_MAX_N];
+  int R, f[ORACLE_MAX_N];
+  sparse_radices(&P, radix, &R);
+  u128 t = 1;
+  for (int d = 0; d < R; ++d) {
+    Q[d] = (uint64_t)t;
+    t *= radix[d];
+    if (t > ((u128)1 << 63)) return -1;
+  }
+  if ((u128)g >= t) return -1;
+  mixed_gray_unrank(g, R, Q, f);
+  *J = sparse_set(&P, f);
   return 0;
 }
 
