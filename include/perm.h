@@ -220,6 +220,58 @@ perm_status perm_repeated_partial(int dtype, const double* dC, int n, int R, int
                                   const perm_opts* opts, perm_result* out, void* stream);
 
 /*
+ * perm_sparse -- per(A) of a sparse n x n matrix by the restricted Ryser sum of
+ * App. B (greedypartition, sparsepermanent).  A set J of columns can give a
+ * nonzero term of Eq. ryser only if every row has a nonzero entry in J.
+ * greedypartition repeatedly takes a remaining row of least degree, makes its
+ * set of nonzero columns a block S_l, and drops every remaining row whose set
+ * meets S_l.  The sum then runs only over the J that meet every block: a
+ * nonempty subset of each S_l times any subset of the other columns T.
+ * 2^|T| prod_l (2^|S_l| - 1) terms instead of 2^n; the value is per(A) exactly
+ * (only zero terms are dropped).  Blocks of more than 12 columns do not restrict
+ * (their columns join T).
+ *   dtype   PERM_DT_REAL, PERM_DT_COMPLEX or PERM_DT_INT01 (bytes 0/1, any nonzero
+ *           byte value is taken as an integer entry).
+ *   dA      device matrix, column-major, ld >= n, 1 <= n <= 64.
+ *   trials  1: the greedy takes the lowest row index among rows of least degree.
+ *           2..256: trial 0 as before, trials 1.. break ties at random (a
+ *           counter-based hash of seed, trial and step), and the partition with the
+ *           fewest column sets is used (the paper's randomised variant).
+ *   The sets are walked in reflected mixed-radix Gray order: one digit per block
+ *   (radix 2^|S_l| - 1, value v standing for the subset gray(v + 1) of the block's
+ *   columns in ascending order), in selection order, then one radix-2 digit per
+ *   column of T (ascending); every step adds or removes one column.
+ *   out->terms is the number of sets; log2_chunk reports the inner digits.
+ *   PERM_DT_INT01: the result is exact (int_lo/int_hi) when the row degrees d_i
+ *   satisfy prod d_i < 2^52 and terms * prod d_i <= 2^100 (FP64 then holds every
+ *   product and partial sum exactly); otherwise PERM_ERANGE.  A zero row gives 0.
+ * Errors: PERM_EINVAL, PERM_ENONFINITE, PERM_ERANGE, PERM_ENOTIMPL (options other
+ *   than log2_chunk <= 14, blocks, no_row_scaling), PERM_EHIP.
+ */
+perm_status perm_sparse(int dtype, const void* dA, int n, int ld, int trials, uint64_t seed,
+                        const perm_opts* opts, perm_result* out, void* stream);
+
+/*
+ * perm_sparse_partial -- the raw sum of Eq. ryser's terms (-1)^|J| prod_i sum_{j in J}
+ * a_ij over Gray indices [start, start + count) of that enumeration, without the
+ * factor (-1)^n; start + count <= out->terms of perm_sparse.  0/1 input gives the
+ * FP64 double-double sum (no exactness check).  Arguments as perm_sparse.
+ */
+perm_status perm_sparse_partial(int dtype, const void* dA, int n, int ld, int trials,
+                                uint64_t seed, uint64_t start, uint64_t count,
+                                const perm_opts* opts, perm_result* out, void* stream);
+
+/*
+ * perm_sparse_partition -- the partition perm_sparse would use: block_of_col (HOST,
+ * n entries) gets the block index of every column in selection order, -1 for T;
+ * *nblocks the number of blocks; *terms the number of column sets.  Waits for
+ * `stream`.  PERM_EINVAL also when A has a zero row.
+ */
+perm_status perm_sparse_partition(int dtype, const void* dA, int n, int ld, int trials,
+                                  uint64_t seed, int32_t* block_of_col, int32_t* nblocks,
+                                  uint64_t* terms, void* stream);
+
+/*
  * perm_band -- permanents of band matrices (a_ij = 0 whenever |i - j| > k) by
  * the transfer matrix of App. C (bandpermanent), one workgroup per matrix.
  *   per(A) is the sum of the coefficients of prod_i (sum_j a_ij x_j) with every

@@ -56,6 +56,13 @@ SIGNATURES = {
     "perm_partial": ([_i, _vp, _i, _i, _u64, _u64, ctypes.POINTER(perm_opts),
                       ctypes.POINTER(perm_result), _vp], _i),
     "perm_batched": ([_vp, _vp, _vp, _i, _i, ctypes.POINTER(perm_opts), _vp, _vp, _vp], _i),
+    "perm_sparse": ([_i, _vp, _i, _i, _i, _u64, ctypes.POINTER(perm_opts),
+                     ctypes.POINTER(perm_result), _vp], _i),
+    "perm_sparse_partial": ([_i, _vp, _i, _i, _i, _u64, _u64, _u64, ctypes.POINTER(perm_opts),
+                             ctypes.POINTER(perm_result), _vp], _i),
+    "perm_sparse_partition": ([_i, _vp, _i, _i, _i, _u64, ctypes.POINTER(ctypes.c_int32),
+                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint64),
+                               _vp], _i),
     "perm_band": ([_i, _vp, _vp, _vp, _i, _i, ctypes.POINTER(perm_opts), _vp, _vp, _vp], _i),
     "perm_repeated": ([_i, _vp, _i, _i, _i, ctypes.POINTER(ctypes.c_int32),
                        ctypes.POINTER(perm_opts), ctypes.POINTER(perm_result), _vp], _i),
@@ -269,6 +276,57 @@ def perm_repeated_partial(C, mult, start: int, count: int, stream=None, **opts) 
                                       ctypes.byref(r), _stream_handle(stream)),
            "perm_repeated_partial")
     return _result(r, False)
+
+
+def _square_cm(A):
+    """(dtype code, pointer, n, ld, tensor) of a square device matrix seen
+    column-major; a row-major tensor is copied (a partial sum or a partition
+    is not invariant under transposition)."""
+    import torch
+    if not isinstance(A, torch.Tensor) or A.device.type != "cuda":
+        raise TypeError("expected a CUDA (HIP) torch tensor")
+    dt = {torch.float64: PERM_DT_REAL, torch.complex128: PERM_DT_COMPLEX,
+          torch.uint8: PERM_DT_INT01}.get(A.dtype)
+    if dt is None:
+        raise TypeError(f"expected float64, complex128 or uint8, got {A.dtype}")
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("expected a square matrix")
+    n = A.shape[0]
+    if n > 1 and A.stride(0) != 1:
+        A = A.t().contiguous().t()
+    ld = A.stride(1) if n > 1 else max(n, 1)
+    return dt, ctypes.c_void_p(A.data_ptr()), n, max(ld, n, 1), A
+
+
+def perm_sparse(A, trials: int = 1, seed: int = 0, stream=None, **opts) -> Result:
+    """per(A) by App. B's restricted Ryser sum (exact for uint8 input within its bound)."""
+    dt, p, n, ld, keep = _square_cm(A)
+    o, r = make_opts(**opts), perm_result()
+    _check(_lib.perm_sparse(dt, p, n, ld, int(trials), int(seed), ctypes.byref(o), ctypes.byref(r),
+                            _stream_handle(stream)), "perm_sparse")
+    return _result(r, dt == PERM_DT_INT01)
+
+
+def perm_sparse_partial(A, start: int, count: int, trials: int = 1, seed: int = 0, stream=None,
+                        **opts) -> Result:
+    """Raw App. B sum (no (-1)^n) over Gray indices [start, start+count) of its enumeration."""
+    dt, p, n, ld, keep = _square_cm(A)
+    o, r = make_opts(**opts), perm_result()
+    _check(_lib.perm_sparse_partial(dt, p, n, ld, int(trials), int(seed), int(start), int(count),
+                                    ctypes.byref(o), ctypes.byref(r), _stream_handle(stream)),
+           "perm_sparse_partial")
+    return _result(r, False)
+
+
+def perm_sparse_partition(A, trials: int = 1, seed: int = 0, stream=None):
+    """(block index of every column or -1, number of blocks, number of column sets)."""
+    dt, p, n, ld, keep = _square_cm(A)
+    blk = (ctypes.c_int32 * n)()
+    nb, terms = ctypes.c_int32(), ctypes.c_uint64()
+    _check(_lib.perm_sparse_partition(dt, p, n, ld, int(trials), int(seed), blk, ctypes.byref(nb),
+                                      ctypes.byref(terms), _stream_handle(stream)),
+           "perm_sparse_partition")
+    return [int(x) for x in blk], nb.value, terms.value
 
 
 def perm_band(A_packed, sizes, offsets, k: int, is_complex: bool, out, status=None, stream=None,

@@ -29,17 +29,17 @@ SOURCES = [
     ("kern_complex.hip", ["-DPERM_HALF=1"]),
     ("kern_int01.hip", ["-DPERM_HALF=0"]),
     ("kern_int01.hip", ["-DPERM_HALF=1"]),
-    ("kern_repeated.hip", ["-DPERM_CPLX=0", "-DPERM_HALF=0"]),
-    ("kern_repeated.hip", ["-DPERM_CPLX=0", "-DPERM_HALF=1"]),
-    ("kern_repeated.hip", ["-DPERM_CPLX=1", "-DPERM_HALF=0"]),
-    ("kern_repeated.hip", ["-DPERM_CPLX=1", "-DPERM_HALF=1"]),
-    ("kern_repeated_stage.hip", []),
+    ("kern_mixed.hip", ["-DPERM_CPLX=0", "-DPERM_HALF=0"]),
+    ("kern_mixed.hip", ["-DPERM_CPLX=0", "-DPERM_HALF=1"]),
+    ("kern_mixed.hip", ["-DPERM_CPLX=1", "-DPERM_HALF=0"]),
+    ("kern_mixed.hip", ["-DPERM_CPLX=1", "-DPERM_HALF=1"]),
+    ("kern_mixed_stage.hip", []),
     ("kern_band.hip", []),
     ("kern_stage.hip", []),
     ("kern_batched.hip", []),
     ("perm_host.cpp", []),
     ("perm_batched.cpp", []),
-    ("perm_repeated.cpp", []),
+    ("perm_mixed.cpp", []),
     ("perm_band.cpp", []),
 ]
 

@@ -1,15 +1,19 @@
-// Walk of Ryser's formula for repeated columns (Sec. II.A, Eq. ryser2).
+// Mixed-radix walk of Ryser-type sums: repeated columns (Sec. II.A,
+// Eq. ryser2) and the restricted column sets of sparse matrices (App. B).
 //
-// Term of the vector f: (-1)^(f_0+...+f_{R-1}) prod_k C(m_k, f_k)
-// prod_i w_i, w_i = sum_k f_k c_ik.  The vectors are taken in reflected
-// mixed-radix Gray order, so from one term to the next a single f_j moves by
-// one and w changes by +-c_j: n additions per term, as in the binary walk of
-// App. A.  One lane walks one chunk (a full run of the inner digits, L terms);
-// the digit j, its direction and the inner weight at step s come from the
-// staged tables (wave-uniform: all chunks of a wave have the same parity), and
-// column c_j is read with scalar loads.  The outer digits are formed afresh
-// from the chunk index at every chunk start, so the walk's rounding does not
-// carry over from chunk to chunk; their weight and sign multiply the chunk sum.
+// Term of the digit vector f: prod_k omega_k(f_k) * prod_i w_i, where w_i is
+// row i's sum over the term's columns (kind 0 digit: f_k copies of column
+// c_k; kind 1 digit: the nonempty subset gray(f_k + 1) of its block) and
+// omega_k(f_k) the digit value's signed weight ((-1)^f C(m, f), or
+// (-1)^|subset|).  The vectors are taken in reflected mixed-radix Gray order,
+// so from one term to the next one digit moves by one and w changes by one
+// column: n additions per term, as in the binary walk of App. A.  One lane
+// walks one chunk (a full run of the inner digits, L terms); the column added
+// at step s and the inner weight come from the staged tables (wave-uniform:
+// all chunks of a wave have the same parity), and the column is read with
+// scalar loads.  The outer digits are formed afresh from the chunk index at
+// every chunk start, so the walk's rounding does not carry over from chunk to
+// chunk; their weight multiplies the chunk sum.
 //
 // Per term: n FP64 additions (complex 2n), the product of the row sums, one
 // multiply by the inner weight, and a double-double lane sum per pair of terms.
@@ -75,26 +79,32 @@ __device__ __forceinline__ void product(const Rows<N>& w, double& pr, double& pi
 }
 
 // Digits k = k0 .. R-1 of q (q = chunk index with k0 = b, or term index with
-// k0 = 0): f_k = a_k or r_k - 1 - a_k by the parity of the digits above
-// (a_k the counting digit); adds f_k c_k to the row sums and multiplies the
-// weight by C(m_k, f_k).  Returns the parity of the digit sum.
+// k0 = 0): f_k = a_k or r_k - 1 - a_k by the parity of the digits above (a_k
+// the counting digit); adds the digit value's columns to the row sums and
+// multiplies the weight by omega_k(f_k).
 template <int N>
-__device__ __forceinline__ uint32_t outer_digits(const RepArgs& a, const double* staged,
-                                                 uint64_t q, int k0, Rows<N>& w, double& W) {
-  ciptr radix = (ciptr)a.radix;
-  uint32_t odd = 0;
+__device__ __forceinline__ void outer_digits(const MixArgs& a, const double* staged, uint64_t q,
+                                             int k0, Rows<N>& w, double& W) {
+  ciptr dig = (ciptr)a.dig;
 #pragma unroll 1
   for (int k = k0; k < a.R; ++k) {
-    const uint32_t r = (uint32_t)radix[k];
+    const uint32_t r = (uint32_t)dig[kDigRadix * kMaxN + k];
+    const int kind = dig[kDigKind * kMaxN + k];
+    const int first = dig[kDigFirst * kMaxN + k];
     const uint64_t qn = q / r;
     const uint32_t dgt = (uint32_t)(q - qn * r);
     q = qn;
     const uint32_t f = (q & 1) ? r - 1u - dgt : dgt;
-    odd ^= f & 1u;
-    W *= a.binom[k * kRepBinomStride + f];
-    add_col_times<N>(w, staged, k, (double)f);
+    W *= a.omega[dig[kDigWofs * kMaxN + k] + f];
+    if (kind == 0) {
+      add_col_times<N>(w, staged, first, (double)f);
+    } else {
+      const uint32_t sub = (f + 1u) ^ ((f + 1u) >> 1);
+      const int size = dig[kDigSize * kMaxN + k];
+#pragma unroll 1
+      for (int e = 0; e < size; ++e) add_col_times<N>(w, staged, first + e, (double)((sub >> e) & 1u));
+    }
   }
-  return odd;
 }
 
 // Exact product of a double-double by a double (TwoProduct on the high part).
@@ -105,7 +115,7 @@ __device__ __forceinline__ dd dd_scale(dd x, double s) {
 }
 
 template <int N>
-__device__ __forceinline__ Acc single_term(const RepArgs& a, uint64_t g) {
+__device__ __forceinline__ Acc single_term(const MixArgs& a, uint64_t g) {
   const double* staged = opaque(a.staged);
   Rows<N> w;
 #pragma unroll
@@ -116,8 +126,7 @@ __device__ __forceinline__ Acc single_term(const RepArgs& a, uint64_t g) {
 #endif
   }
   double W = 1.0;
-  const uint32_t odd = outer_digits<N>(a, staged, g, 0, w, W);
-  if (odd) W = -W;
+  outer_digits<N>(a, staged, g, 0, w, W);
   double pr, pi;
   product<N>(w, pr, pi);
   const double hr = W * pr, hi = W * pi;
@@ -125,11 +134,11 @@ __device__ __forceinline__ Acc single_term(const RepArgs& a, uint64_t g) {
 }
 
 template <int N>
-__device__ __forceinline__ Acc walk_chunk(const RepArgs& a, uint64_t c, uint32_t par) {
+__device__ __forceinline__ Acc walk_chunk(const MixArgs& a, uint64_t c, uint32_t par) {
   const double* staged = opaque(a.staged);
   Rows<N> w;
   {
-    cdptr st = as_const(staged + kCw * (2 * (a.R + 1) + (int)par) * N);
+    cdptr st = as_const(staged + kCw * (2 * (a.ncols + 1) + (int)par) * N);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       w.r[i] = st[kCw * i];
@@ -139,7 +148,7 @@ __device__ __forceinline__ Acc walk_chunk(const RepArgs& a, uint64_t c, uint32_t
     }
   }
   double W = 1.0;
-  const uint32_t odd = outer_digits<N>(a, staged, c, a.b, w, W);
+  outer_digits<N>(a, staged, c, a.b, w, W);
   cdptr tin = as_const(a.tin + par * (uint32_t)a.L);
   ciptr toff = (ciptr)(a.toff + par * (uint32_t)a.L);
   Acc acc{{0.0, 0.0}, {0.0, 0.0}};
@@ -166,12 +175,11 @@ __device__ __forceinline__ Acc walk_chunk(const RepArgs& a, uint64_t c, uint32_t
     dd_acc(acc.im, tin[s] * pi);
 #endif
   }
-  if (odd) W = -W;
   return Acc{dd_scale(acc.re, W), dd_scale(acc.im, W)};
 }
 
 template <int N, bool SINGLE>
-__global__ __launch_bounds__(kBlock) void rep_walk_kernel(RepArgs a) {
+__global__ __launch_bounds__(kBlock) void mix_walk_kernel(MixArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint64_t wave = wave_id();
   const uint64_t nwaves = (uint64_t)gridDim.x * kWavesPerBlock;
@@ -215,11 +223,11 @@ __global__ __launch_bounds__(kBlock) void rep_walk_kernel(RepArgs a) {
 }
 
 template <int N>
-hipError_t dispatch(bool single, const RepArgs& a, int grid, hipStream_t s) {
+hipError_t dispatch(bool single, const MixArgs& a, int grid, hipStream_t s) {
   if (single)
-    hipLaunchKernelGGL((rep_walk_kernel<N, true>), dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((mix_walk_kernel<N, true>), dim3(grid), dim3(kBlock), 0, s, a);
   else
-    hipLaunchKernelGGL((rep_walk_kernel<N, false>), dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((mix_walk_kernel<N, false>), dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
@@ -233,15 +241,15 @@ hipError_t dispatch(bool single, const RepArgs& a, int grid, hipStream_t s) {
 // n = 1..32 or n = 33..64.
 #if PERM_CPLX
 #if PERM_HALF == 0
-#define PERM_LAUNCH launch_rep_walk_complex_lo
+#define PERM_LAUNCH launch_mix_walk_complex_lo
 #else
-#define PERM_LAUNCH launch_rep_walk_complex_hi
+#define PERM_LAUNCH launch_mix_walk_complex_hi
 #endif
 #else
 #if PERM_HALF == 0
-#define PERM_LAUNCH launch_rep_walk_real_lo
+#define PERM_LAUNCH launch_mix_walk_real_lo
 #else
-#define PERM_LAUNCH launch_rep_walk_real_hi
+#define PERM_LAUNCH launch_mix_walk_real_hi
 #endif
 #endif
 #if PERM_HALF == 0
@@ -250,7 +258,7 @@ hipError_t dispatch(bool single, const RepArgs& a, int grid, hipStream_t s) {
 #define PERM_CASES "perm_cases_hi.inc"
 #endif
 
-hipError_t PERM_LAUNCH(int n, bool single, const RepArgs& a, int grid, hipStream_t s) {
+hipError_t PERM_LAUNCH(int n, bool single, const MixArgs& a, int grid, hipStream_t s) {
   switch (n) {
 #include PERM_CASES
     default:

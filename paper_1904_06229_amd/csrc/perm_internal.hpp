@@ -119,48 +119,88 @@ hipError_t launch_batched_finish(const double* slots, const int64_t* item_first,
 // Resident workgroups per CU of the persistent kernel for this configuration.
 int batched_walk_blocks_per_cu(int is_complex, int mode, int max_n);
 
-// ------------------------------------------------------ repeated columns ----
-// Eq. ryser2 walk (perm_repeated): the vectors f (0 <= f_k <= m_k) in
-// reflected mixed-radix Gray order, radix r_k = m_k + 1, digit 0 fastest.
-// A chunk is one run of the first b digits through all L = r_0...r_{b-1}
-// values, i.e. Gray indices [c L, (c+1) L).  Inside it the digit changed at
-// step s, its direction, and the weight of the inner digits depend only on s
-// and the parity of c (tables tin/toff, built by the staging kernel); the
-// lane -> chunk map gives all lanes of a wave chunks of one parity.
+// ------------------------------------------------------ mixed-radix sums ----
+// Ryser-type sums whose column sets are enumerated digit by digit: repeated
+// columns (Eq. ryser2; perm_repeated) and the restricted sets of sparse
+// matrices (App. B; perm_sparse).  Digit k has radix r_k and takes values
+// f_k in reflected mixed-radix Gray order (digit 0 fastest), so one step
+// changes one digit by one and adds or removes one column:
+//   kind 0 (a column with multiplicity m): value f adds f * c, weight
+//          (-1)^f C(m, f); one column (`size` 1);
+//   kind 1 (a block of `size` columns that the set must meet): value v
+//          stands for the nonempty subset gray(v + 1) of the block's columns,
+//          weight (-1)^|subset|.
+// The signed weights of every digit value sit in one table (omega).  A chunk
+// is one run of the first b digits through all L = r_0...r_{b-1} values;
+// inside it the changed digit, its direction and the inner weight depend only
+// on the step and the chunk's parity (tables tin/toff), and the lane -> chunk
+// map gives all lanes of a wave one parity.
 
-constexpr int kRepBinomStride = kMaxN + 1;  // binom table row: C(m_k, 0..64)
-constexpr int kRepMaxLog2Chunk = 14;        // L <= 2^14
+constexpr int kRepBinomStride = kMaxN + 1;  // largest radix of a kind-0 digit (m <= 64)
+constexpr int kMixMaxLog2Chunk = 14;        // L <= 2^14
+constexpr int kSparseMaxBlock = 12;         // blocks of more columns do not restrict
+constexpr int kMixMaxOmega = kMaxN * 4096;  // omega table entries
 
-struct RepMult {
-  int32_t m[kMaxN];
+struct MixDigits {
+  int32_t R;              // digits
+  int32_t ncols;          // staged columns (sum of the sizes)
+  int32_t kind[kMaxN];
+  int32_t radix[kMaxN];
+  int32_t first[kMaxN];   // first staged column of the digit
+  int32_t size[kMaxN];    // staged columns of the digit
+  int32_t mult[kMaxN];    // kind 0: multiplicity m
+  int32_t src[kMaxN];     // staged column c is source column src[c]
+  int32_t cmult[kMaxN];   // copies of staged column c in the matrix (row-norm weight)
 };
 
-struct RepArgs {
-  const double* staged;   // [+C | 0] [-C | 0] (n x (R+1) each), then the two start columns
-  const double* binom;    // R x kRepBinomStride: C(m_k, f) as doubles
+// Device copy of the digit description, read with scalar loads by the walk.
+enum { kDigRadix = 0, kDigKind = 1, kDigFirst = 2, kDigSize = 3, kDigWofs = 4, kDigFields = 5 };
+
+struct MixArgs {
+  const double* staged;   // [+cols | 0] [-cols | 0] (n x (ncols+1) each), then two start columns
+  const double* omega;    // signed weight of every digit value
   const double* tin;      // 2 x L: signed weight of the inner digits at step s (parity 0, 1)
   const int32_t* toff;    // 2 x L: offset (doubles) into staged of the column added after
                           // step s; the last step adds the zero column
-  const int32_t* radix;   // R radices m_k + 1
+  const int32_t* dig;     // kDigFields x kMaxN digit fields
   const int32_t* status;  // staging status; nonzero -> the walk does nothing
   uint64_t first;         // first chunk (walk) or first Gray index (single terms)
   uint64_t nchunks;
   uint64_t ntasks;        // 2 * ceil(nchunks / 128)
-  int32_t R, b, L, pad;
+  int32_t R, b, L, ncols;
   void* partials;         // per workgroup: dd (real) or complex dd
 };
 
-hipError_t launch_rep_stage(int is_complex, const double* C, int n, int R, int ld,
-                            const RepMult& mult, int b, int L, int row_scaling, double* staged,
-                            double* binom, double* tin, int32_t* toff, int32_t* radix,
-                            int32_t* rowexp, int32_t* status, hipStream_t s);
+// in_kind: 0 real doubles, 1 complex pairs, 2 bytes (0/1 data, staged as doubles).
+hipError_t launch_mix_stage(int in_kind, const void* A, int n, int ld, const MixDigits& dg,
+                            int b, int L, int row_scaling, double* staged, double* omega,
+                            double* tin, int32_t* toff, int32_t* dig, int32_t* rowexp,
+                            int32_t* status, hipStream_t s);
 // single: every lane sums one term (Gray indices first .. first + nchunks - 1).
-hipError_t launch_rep_walk_real_lo(int n, bool single, const RepArgs& a, int grid, hipStream_t s);
-hipError_t launch_rep_walk_real_hi(int n, bool single, const RepArgs& a, int grid, hipStream_t s);
-hipError_t launch_rep_walk_complex_lo(int n, bool single, const RepArgs& a, int grid,
+hipError_t launch_mix_walk_real_lo(int n, bool single, const MixArgs& a, int grid, hipStream_t s);
+hipError_t launch_mix_walk_real_hi(int n, bool single, const MixArgs& a, int grid, hipStream_t s);
+hipError_t launch_mix_walk_complex_lo(int n, bool single, const MixArgs& a, int grid,
                                       hipStream_t s);
-hipError_t launch_rep_walk_complex_hi(int n, bool single, const RepArgs& a, int grid,
+hipError_t launch_mix_walk_complex_hi(int n, bool single, const MixArgs& a, int grid,
                                       hipStream_t s);
+
+// App. B greedypartition on the device.  Trial 0 takes the lowest row index
+// among rows of least degree; trials 1.. break ties with a counter-based hash
+// of (seed, trial, step); the trial with the fewest column sets wins (lowest
+// trial on ties).
+struct SparsePart {
+  int32_t status;         // 0, or 1 when a row is zero (per = 0)
+  int32_t nblocks;
+  int32_t ntail;
+  int32_t trial;          // winning trial
+  int32_t cols[kMaxN];    // blocks in selection order (columns ascending), then T ascending
+  int32_t bsize[kMaxN];
+  double log2_terms;      // log2 of 2^|T| prod (2^|S| - 1)
+  double log2_degprod;    // log2 prod_i (nonzeros of row i)
+};
+
+hipError_t launch_sparse_partition(int in_kind, const void* A, int n, int ld, int trials,
+                                   uint64_t seed, SparsePart* out, hipStream_t s);
 
 // ------------------------------------------------------------------ band ----
 // App. C transfer matrix (perm_band): one workgroup per matrix.

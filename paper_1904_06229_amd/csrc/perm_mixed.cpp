@@ -1,0 +1,495 @@
+// C-ABI entry points of the mixed-radix Ryser walks: perm_repeated and
+// perm_repeated_partial (repeated columns, Eq. ryser2), perm_sparse,
+// perm_sparse_partial and perm_sparse_partition (sparse matrices, App. B).
+//
+// Launch sequence (caller's stream): [sparse: greedypartition on the device,
+// then one small record back to the host] -> stage (checks, row exponents,
+// +cols/-cols, digit weights, the inner-digit step tables) -> walk: head
+// (single terms), body (chunks of L terms), tail (single terms) -> the
+// fixed-order finish shared with the dense path -> copy of one record ->
+// wait -> (-1)^n and the row scaling.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "../../include/perm.h"
+#include "perm_batched_host.hpp"
+#include "perm_internal.hpp"
+
+using namespace perm;
+
+namespace {
+
+constexpr int kMaxGrid = 65536;  // workgroups per walk launch
+constexpr int kMaxMixParts = 3 * kMaxGrid;
+constexpr int kMaxSparseTrials = 256;
+
+struct MixWorkspace {
+  int device = -1;
+  int cu_count = 256;
+  char* dmem = nullptr;
+  DevResult* hres = nullptr;
+  SparsePart* hpart = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  int32_t* status = nullptr;
+  int32_t* rowexp = nullptr;
+  int32_t* dig = nullptr;
+  DevResult* dres = nullptr;
+  SparsePart* dpart = nullptr;
+  double* staged = nullptr;
+  double* omega = nullptr;
+  double* tin = nullptr;
+  int32_t* toff = nullptr;
+  void* partials = nullptr;
+};
+
+std::mutex g_mu;
+std::map<int, MixWorkspace*> g_ws;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+perm_status hip_fail(const char* what, hipError_t e) {
+  return set_error(PERM_EHIP, (std::string(what) + " failed: " + hipGetErrorString(e)).c_str());
+}
+
+#define MIX_TRY(expr)                                 \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) return hip_fail(#expr, e_); \
+  } while (0)
+
+perm_status get_ws(MixWorkspace** out) {
+  int dev = 0;
+  MIX_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_ws.find(dev);
+  if (it != g_ws.end()) {
+    *out = it->second;
+    return PERM_OK;
+  }
+  const size_t L = (size_t)1 << kMixMaxLog2Chunk;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  const size_t o_status = take(64);
+  const size_t o_rowexp = take(sizeof(int32_t) * kMaxN);
+  const size_t o_dig = take(sizeof(int32_t) * kDigFields * kMaxN);
+  const size_t o_res = take(sizeof(DevResult));
+  const size_t o_part = take(sizeof(SparsePart));
+  const size_t o_staged = take(sizeof(double) * 2 * (2 * (kMaxN + 1) + 2) * kMaxN);
+  const size_t o_omega = take(sizeof(double) * kMixMaxOmega);
+  const size_t o_tin = take(sizeof(double) * 2 * L);
+  const size_t o_toff = take(sizeof(int32_t) * 2 * L);
+  const size_t o_parts = take(sizeof(double) * 4 * (size_t)kMaxMixParts);
+  MixWorkspace* w = new MixWorkspace();
+  w->device = dev;
+  if (hipMalloc((void**)&w->dmem, off) != hipSuccess) {
+    delete w;
+    return set_error(PERM_ENOMEM, "hipMalloc of the mixed-radix workspace failed");
+  }
+  if (hipHostMalloc((void**)&w->hres, sizeof(DevResult), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&w->hpart, sizeof(SparsePart), hipHostMallocDefault) != hipSuccess) {
+    if (w->hres) (void)hipHostFree(w->hres);
+    (void)hipFree(w->dmem);
+    delete w;
+    return set_error(PERM_ENOMEM, "hipHostMalloc failed");
+  }
+  for (auto& ev : w->ev) MIX_TRY(hipEventCreate(&ev));
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+    w->cu_count = prop.multiProcessorCount;
+  w->status = (int32_t*)(w->dmem + o_status);
+  w->rowexp = (int32_t*)(w->dmem + o_rowexp);
+  w->dig = (int32_t*)(w->dmem + o_dig);
+  w->dres = (DevResult*)(w->dmem + o_res);
+  w->dpart = (SparsePart*)(w->dmem + o_part);
+  w->staged = (double*)(w->dmem + o_staged);
+  w->omega = (double*)(w->dmem + o_omega);
+  w->tin = (double*)(w->dmem + o_tin);
+  w->toff = (int32_t*)(w->dmem + o_toff);
+  w->partials = (void*)(w->dmem + o_parts);
+  g_ws[dev] = w;
+  *out = w;
+  return PERM_OK;
+}
+
+int floor_log2(uint64_t x) { return x ? 63 - __builtin_clzll(x) : -1; }
+
+hipError_t launch_walk(bool cplx, int n, bool single, const MixArgs& a, int grid, hipStream_t s) {
+  if (cplx)
+    return n <= 32 ? launch_mix_walk_complex_lo(n, single, a, grid, s)
+                   : launch_mix_walk_complex_hi(n, single, a, grid, s);
+  return n <= 32 ? launch_mix_walk_real_lo(n, single, a, grid, s)
+                 : launch_mix_walk_real_hi(n, single, a, grid, s);
+}
+
+// The options the mixed-radix walks take: precision PERM_FP64_DD, log2_chunk
+// <= 14, blocks, row scaling.
+perm_status check_opts(const perm_opts& o) {
+  if (o.precision != PERM_FP64_DD)
+    return set_error(PERM_ENOTIMPL, "mixed-radix walks: only PERM_FP64_DD is provided");
+  if (o.drift_check) return set_error(PERM_ENOTIMPL, "mixed-radix walks: no drift check");
+  if (o.use_graph) return set_error(PERM_ENOTIMPL, "mixed-radix walks: no graph replay");
+  if (o.log2_chunk < 0 || o.log2_chunk > kMixMaxLog2Chunk)
+    return set_error(PERM_EINVAL, "log2_chunk out of range (max 14)");
+  if (o.blocks < 0 || o.blocks > kMaxGrid) return set_error(PERM_EINVAL, "blocks out of range");
+  if (o.reserved[0] || o.reserved[1]) return set_error(PERM_EINVAL, "reserved options must be 0");
+  return PERM_OK;
+}
+
+struct Walked {
+  DevResult res;
+  int b;
+  uint64_t chunks;
+  int blocks;
+  float kernel_ms, total_ms;
+};
+
+// Stage and walk Gray indices [start, start + count) of the digit order.
+perm_status run_mixed(MixWorkspace* ws, int in_kind, const void* dA, int n, int ld,
+                      const MixDigits& dg, uint64_t start, uint64_t count, const perm_opts& o,
+                      int row_scaling, hipStream_t stream, Walked* wk) {
+  const bool cplx = in_kind == 1;
+  // Inner digits: as many leading digits as fit in the chunk cap (at least one).
+  int cap_lg = o.log2_chunk;
+  if (cap_lg == 0) {
+    cap_lg = floor_log2(count) - 18;
+    cap_lg = cap_lg < 4 ? 4 : (cap_lg > 12 ? 12 : cap_lg);
+  }
+  const uint64_t cap = 1ull << cap_lg;
+  int b = 0;
+  uint64_t L = 1;
+  while (b < dg.R && L * (uint64_t)dg.radix[b] <= cap) L *= (uint64_t)dg.radix[b++];
+  if (b == 0) {
+    b = 1;
+    L = (uint64_t)dg.radix[0];
+  }
+  const uint64_t end = start + count;
+  uint64_t a0 = (start + L - 1) / L * L;
+  if (a0 > end) a0 = end;
+  const uint64_t a1 = a0 + (end - a0) / L * L;
+  const int grid_cap = o.blocks > 0 ? o.blocks : 8 * ws->cu_count;
+  MIX_TRY(hipEventRecord(ws->ev[0], stream));
+  MIX_TRY(launch_mix_stage(in_kind, dA, n, ld, dg, b, (int)L, row_scaling, ws->staged, ws->omega,
+                           ws->tin, ws->toff, ws->dig, ws->rowexp, ws->status, stream));
+  int nparts = 0, body_grid = 0;
+  const size_t part_bytes = cplx ? 32 : 16;
+  auto walk = [&](uint64_t first, uint64_t nchunks, bool single, int* grid_out) -> perm_status {
+    if (nchunks == 0) return PERM_OK;
+    MixArgs a;
+    a.staged = ws->staged;
+    a.omega = ws->omega;
+    a.tin = ws->tin;
+    a.toff = ws->toff;
+    a.dig = ws->dig;
+    a.status = ws->status;
+    a.first = first;
+    a.nchunks = nchunks;
+    a.ntasks = 2 * ((nchunks + 2 * kWave - 1) / (2 * kWave));
+    a.R = dg.R;
+    a.b = b;
+    a.L = (int32_t)L;
+    a.ncols = dg.ncols;
+    a.partials = (char*)ws->partials + part_bytes * nparts;
+    uint64_t blocks = (a.ntasks + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks > (uint64_t)grid_cap) blocks = (uint64_t)grid_cap;
+    if (blocks < 1) blocks = 1;
+    const int grid = (int)blocks;
+    if (grid_out) *grid_out = grid;
+    nparts += grid;
+    const hipError_t e = launch_walk(cplx, n, single, a, grid, stream);
+    if (e != hipSuccess) return hip_fail("mixed-radix walk launch", e);
+    return PERM_OK;
+  };
+  perm_status st;
+  MIX_TRY(hipEventRecord(ws->ev[1], stream));
+  if ((st = walk(start, a0 - start, true, nullptr)) != PERM_OK) return st;
+  if ((st = walk(a0 / L, (a1 - a0) / L, false, &body_grid)) != PERM_OK) return st;
+  if ((st = walk(a1, end - a1, true, nullptr)) != PERM_OK) return st;
+  MIX_TRY(hipEventRecord(ws->ev[2], stream));
+  MIX_TRY(launch_finish(cplx ? kComplex : kReal, ws->partials, nparts, nullptr, 0, ws->status,
+                        ws->rowexp, n, nullptr, ws->dres, stream));
+  MIX_TRY(hipMemcpyAsync(ws->hres, ws->dres, sizeof(DevResult), hipMemcpyDeviceToHost, stream));
+  MIX_TRY(hipEventRecord(ws->ev[3], stream));
+  MIX_TRY(hipStreamSynchronize(stream));
+  wk->res = *ws->hres;
+  wk->b = b;
+  wk->chunks = (a1 - a0) / L + (a0 - start) + (end - a1);
+  wk->blocks = body_grid;
+  wk->kernel_ms = wk->total_ms = 0.0f;
+  (void)hipEventElapsedTime(&wk->kernel_ms, ws->ev[1], ws->ev[2]);
+  (void)hipEventElapsedTime(&wk->total_ms, ws->ev[0], ws->ev[3]);
+  if (wk->res.status == kStNonFinite)
+    return set_error(PERM_ENONFINITE, "matrix has a NaN or infinite entry");
+  if (wk->res.status != kStOk) return set_error(PERM_EHIP, "unexpected device status");
+  return PERM_OK;
+}
+
+// Product of the radices, or 0 above 2^63.
+uint64_t digit_terms(const MixDigits& dg) {
+  unsigned __int128 t = 1;
+  for (int k = 0; k < dg.R; ++k) {
+    t *= (unsigned __int128)dg.radix[k];
+    if (t > ((unsigned __int128)1 << 63)) return 0;
+  }
+  return (uint64_t)t;
+}
+
+void fill_float(const Walked& wk, double sign, uint64_t count, perm_result* r) {
+  const int e = -wk.res.exp_sum;
+  r->re_hi = std::ldexp(sign * wk.res.v[0], e);
+  r->re_lo = std::ldexp(sign * wk.res.v[1], e);
+  r->im_hi = std::ldexp(sign * wk.res.v[2], e);
+  r->im_lo = std::ldexp(sign * wk.res.v[3], e);
+  r->max_drift = -1.0;
+  r->terms = count;
+  r->chunks = wk.chunks;
+  r->log2_chunk = wk.b;
+  r->blocks = wk.blocks;
+  r->kernel_ms = wk.kernel_ms;
+  r->total_ms = wk.total_ms;
+}
+
+// ------------------------------------------------------- repeated columns ----
+
+perm_status rep_call(int dtype, const double* dC, int n, int R, int ld, const int32_t* mult,
+                     bool whole, uint64_t start, uint64_t count, const perm_opts* opts,
+                     perm_result* out, hipStream_t stream) {
+  if (!out) return set_error(PERM_EINVAL, "out is NULL");
+  if (dtype != PERM_DT_REAL && dtype != PERM_DT_COMPLEX)
+    return set_error(PERM_EINVAL, "dtype must be PERM_DT_REAL or PERM_DT_COMPLEX");
+  if (n < 1 || n > kMaxN) return set_error(PERM_EINVAL, "n must be in [1, 64]");
+  if (R < 1 || R > n) return set_error(PERM_EINVAL, "R must be in [1, n]");
+  if (ld < n) return set_error(PERM_EINVAL, "ld must be >= n");
+  if (!dC || !mult) return set_error(PERM_EINVAL, "NULL argument");
+  MixDigits dg;
+  std::memset(&dg, 0, sizeof dg);
+  dg.R = R;
+  dg.ncols = R;
+  int total = 0;
+  for (int k = 0; k < R; ++k) {
+    if (mult[k] < 1) return set_error(PERM_EINVAL, "every multiplicity must be >= 1");
+    total += mult[k];
+    if (total > n) break;
+    dg.kind[k] = 0;
+    dg.radix[k] = mult[k] + 1;
+    dg.first[k] = k;
+    dg.size[k] = 1;
+    dg.mult[k] = mult[k];
+    dg.src[k] = k;
+    dg.cmult[k] = mult[k];
+  }
+  if (total != n) return set_error(PERM_EINVAL, "the multiplicities must add up to n");
+  const uint64_t T = digit_terms(dg);
+  if (T == 0) return set_error(PERM_EINVAL, "prod (mult[k] + 1) exceeds 2^63");
+  if (whole) {
+    start = 0;
+    count = T;
+  }
+  if (start > T || count > T - start)
+    return set_error(PERM_EINVAL, "range outside [0, prod (mult[k] + 1))");
+  perm_opts o{};
+  if (opts) o = *opts;
+  perm_status st = check_opts(o);
+  if (st != PERM_OK) return st;
+  perm_result r{};
+  r.max_drift = -1.0;
+  if (count == 0) {
+    *out = r;
+    return PERM_OK;
+  }
+  MixWorkspace* ws = nullptr;
+  if ((st = get_ws(&ws)) != PERM_OK) return st;
+  Walked wk;
+  st = run_mixed(ws, dtype == PERM_DT_COMPLEX ? 1 : 0, dC, n, ld, dg, start, count, o,
+                 o.no_row_scaling ? 0 : 1, stream, &wk);
+  if (st != PERM_OK) return st;
+  fill_float(wk, (whole && (n % 2)) ? -1.0 : 1.0, count, &r);  // per = (-1)^n S
+  *out = r;
+  return PERM_OK;
+}
+
+// ---------------------------------------------------------------- sparse ----
+
+perm_status sparse_args(int dtype, const void* dA, int n, int ld, int trials, perm_result* out) {
+  if (!out) return set_error(PERM_EINVAL, "out is NULL");
+  if (dtype < PERM_DT_REAL || dtype > PERM_DT_INT01) return set_error(PERM_EINVAL, "bad dtype");
+  if (n < 1 || n > kMaxN) return set_error(PERM_EINVAL, "n must be in [1, 64]");
+  if (ld < n) return set_error(PERM_EINVAL, "ld must be >= n");
+  if (!dA) return set_error(PERM_EINVAL, "dA is NULL");
+  if (trials < 1 || trials > kMaxSparseTrials)
+    return set_error(PERM_EINVAL, "trials must be in [1, 256]");
+  return PERM_OK;
+}
+
+int in_kind_of(int dtype) { return dtype == PERM_DT_COMPLEX ? 1 : (dtype == PERM_DT_INT01 ? 2 : 0); }
+
+// greedypartition on the device, brought back to the host.
+perm_status partition(MixWorkspace* ws, int dtype, const void* dA, int n, int ld, int trials,
+                      uint64_t seed, hipStream_t stream, SparsePart* part) {
+  MIX_TRY(launch_sparse_partition(in_kind_of(dtype), dA, n, ld, trials, seed, ws->dpart, stream));
+  MIX_TRY(hipMemcpyAsync(ws->hpart, ws->dpart, sizeof(SparsePart), hipMemcpyDeviceToHost, stream));
+  MIX_TRY(hipStreamSynchronize(stream));
+  *part = *ws->hpart;
+  return PERM_OK;
+}
+
+// Digits of the sparse enumeration: blocks (kind 1), then the columns of T.
+void sparse_digits(const SparsePart& p, int n, MixDigits* dg) {
+  std::memset(dg, 0, sizeof *dg);
+  int c = 0, d = 0;
+  for (int l = 0; l < p.nblocks; ++l, ++d) {
+    dg->kind[d] = 1;
+    dg->radix[d] = (1 << p.bsize[l]) - 1;
+    dg->first[d] = c;
+    dg->size[d] = p.bsize[l];
+    c += p.bsize[l];
+  }
+  for (int t = 0; t < p.ntail; ++t, ++d) {
+    dg->kind[d] = 0;
+    dg->radix[d] = 2;
+    dg->first[d] = c++;
+    dg->size[d] = 1;
+    dg->mult[d] = 1;
+  }
+  dg->R = d;
+  dg->ncols = n;
+  for (int j = 0; j < n; ++j) {
+    dg->src[j] = p.cols[j];
+    dg->cmult[j] = 1;
+  }
+}
+
+perm_status sparse_call(int dtype, const void* dA, int n, int ld, int trials, uint64_t seed,
+                        bool whole, uint64_t start, uint64_t count, const perm_opts* opts,
+                        perm_result* out, hipStream_t stream) {
+  perm_status st = sparse_args(dtype, dA, n, ld, trials, out);
+  if (st != PERM_OK) return st;
+  perm_opts o{};
+  if (opts) o = *opts;
+  if ((st = check_opts(o)) != PERM_OK) return st;
+  MixWorkspace* ws = nullptr;
+  if ((st = get_ws(&ws)) != PERM_OK) return st;
+  SparsePart p;
+  if ((st = partition(ws, dtype, dA, n, ld, trials, seed, stream, &p)) != PERM_OK) return st;
+  perm_result r{};
+  r.max_drift = -1.0;
+  if (p.status) {  // a zero row: per(A) = 0 and nothing to enumerate
+    if (!whole && (start != 0 || count != 0))
+      return set_error(PERM_EINVAL, "range outside the (empty) enumeration");
+    *out = r;
+    return PERM_OK;
+  }
+  MixDigits dg;
+  sparse_digits(p, n, &dg);
+  const uint64_t T = digit_terms(dg);
+  if (T == 0) return set_error(PERM_EINVAL, "the enumeration has more than 2^63 column sets");
+  if (whole) {
+    start = 0;
+    count = T;
+  }
+  if (start > T || count > T - start) return set_error(PERM_EINVAL, "range outside [0, terms)");
+  const bool exact = dtype == PERM_DT_INT01;
+  if (exact && whole && !(p.log2_degprod < 52.0 && std::log2((double)T) + p.log2_degprod <= 100.0))
+    return set_error(PERM_ERANGE,
+                     "0/1 sparse path: products or sums may exceed the exact FP64 range");
+  if (count == 0) {
+    *out = r;
+    return PERM_OK;
+  }
+  Walked wk;
+  st = run_mixed(ws, in_kind_of(dtype), dA, n, ld, dg, start, count, o,
+                 (exact || o.no_row_scaling) ? 0 : 1, stream, &wk);
+  if (st != PERM_OK) return st;
+  fill_float(wk, (whole && (n % 2)) ? -1.0 : 1.0, count, &r);
+  if (exact && whole) {
+    // integer row sums, products below 2^52 and a sum below 2^100: hi and lo
+    // are integers and hi + lo is the permanent
+    const __int128 v = (__int128)r.re_hi + (__int128)r.re_lo;
+    r.int_lo = (uint64_t)(unsigned __int128)v;
+    r.int_hi = (int64_t)(v >> 64);
+  }
+  *out = r;
+  return PERM_OK;
+}
+
+}  // namespace
+
+namespace perm {
+void repeated_release() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (auto& kv : g_ws) {
+    MixWorkspace* w = kv.second;
+    (void)hipSetDevice(w->device);
+    (void)hipDeviceSynchronize();
+    for (auto& ev : w->ev)
+      if (ev) (void)hipEventDestroy(ev);
+    if (w->hres) (void)hipHostFree(w->hres);
+    if (w->hpart) (void)hipHostFree(w->hpart);
+    if (w->dmem) (void)hipFree(w->dmem);
+    delete w;
+  }
+  g_ws.clear();
+  (void)hipSetDevice(cur);
+}
+}  // namespace perm
+
+extern "C" {
+
+perm_status perm_repeated(int dtype, const double* dC, int n, int R, int ld, const int32_t* mult,
+                          const perm_opts* opts, perm_result* out, void* stream) {
+  return rep_call(dtype, dC, n, R, ld, mult, true, 0, 0, opts, out, (hipStream_t)stream);
+}
+
+perm_status perm_repeated_partial(int dtype, const double* dC, int n, int R, int ld,
+                                  const int32_t* mult, uint64_t start, uint64_t count,
+                                  const perm_opts* opts, perm_result* out, void* stream) {
+  return rep_call(dtype, dC, n, R, ld, mult, false, start, count, opts, out, (hipStream_t)stream);
+}
+
+perm_status perm_sparse(int dtype, const void* dA, int n, int ld, int trials, uint64_t seed,
+                        const perm_opts* opts, perm_result* out, void* stream) {
+  return sparse_call(dtype, dA, n, ld, trials, seed, true, 0, 0, opts, out, (hipStream_t)stream);
+}
+
+perm_status perm_sparse_partial(int dtype, const void* dA, int n, int ld, int trials,
+                                uint64_t seed, uint64_t start, uint64_t count,
+                                const perm_opts* opts, perm_result* out, void* stream) {
+  return sparse_call(dtype, dA, n, ld, trials, seed, false, start, count, opts, out,
+                     (hipStream_t)stream);
+}
+
+perm_status perm_sparse_partition(int dtype, const void* dA, int n, int ld, int trials,
+                                  uint64_t seed, int32_t* block_of_col, int32_t* nblocks,
+                                  uint64_t* terms, void* stream) {
+  perm_result dummy;
+  perm_status st = sparse_args(dtype, dA, n, ld, trials, &dummy);
+  if (st != PERM_OK) return st;
+  if (!block_of_col || !nblocks || !terms) return set_error(PERM_EINVAL, "NULL argument");
+  MixWorkspace* ws = nullptr;
+  if ((st = get_ws(&ws)) != PERM_OK) return st;
+  SparsePart p;
+  if ((st = partition(ws, dtype, dA, n, ld, trials, seed, (hipStream_t)stream, &p)) != PERM_OK)
+    return st;
+  if (p.status) return set_error(PERM_EINVAL, "the matrix has a zero row (per = 0)");
+  for (int j = 0; j < n; ++j) block_of_col[j] = -1;
+  int c = 0;
+  for (int l = 0; l < p.nblocks; ++l)
+    for (int e = 0; e < p.bsize[l]; ++e) block_of_col[p.cols[c++]] = l;
+  *nblocks = p.nblocks;
+  MixDigits dg;
+  sparse_digits(p, n, &dg);
+  *terms = digit_terms(dg);
+  return PERM_OK;
+}
+
+}  // extern "C"
