@@ -306,7 +306,7 @@ def bench_repeated(args):
         "roofline": {"bound": "alu", "achieved": alg / (kavg * 1e-3) / 1e12,
                      "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
                      "frac": alg / (kavg * 1e-3) / PEAK_LANE_OPS, "traffic": None,
-                     "kernel": f"rep_walk_kernel<{n}, false> (complex)", "kernel_ms": kavg,
+                     "kernel": f"mix_walk_kernel<{n}, false> (complex)", "kernel_ms": kavg,
                      "ops_per_launch": alg},
         "result": repr(complex(r.re_hi + r.re_lo, r.im_hi + r.im_lo)),
     }

@@ -242,9 +242,12 @@ perm_status perm_repeated_partial(int dtype, const double* dC, int n, int R, int
  *   columns in ascending order), in selection order, then one radix-2 digit per
  *   column of T (ascending); every step adds or removes one column.
  *   out->terms is the number of sets; log2_chunk reports the inner digits.
- *   PERM_DT_INT01: the result is exact (int_lo/int_hi) when the row degrees d_i
- *   satisfy prod d_i < 2^52 and terms * prod d_i <= 2^100 (FP64 then holds every
- *   product and partial sum exactly); otherwise PERM_ERANGE.  A zero row gives 0.
+ *   PERM_DT_INT01: exact.  The row sums are integers; every product is formed
+ *   exactly in row groups and summed in 51-bit integer bins folded into a 128-bit
+ *   integer (as perm_int01; chunks of at most 2^10 terms).  The result (int_lo/int_hi,
+ *   and its nearest double pair in re_hi + re_lo) is exact when |per| < 2^127; the
+ *   library checks Bregman's bound sum_i log2(d_i!)/d_i < 127 (d_i = row degrees) and
+ *   returns PERM_ERANGE otherwise.  A zero row gives 0.
  * Errors: PERM_EINVAL, PERM_ENONFINITE, PERM_ERANGE, PERM_ENOTIMPL (options other
  *   than log2_chunk <= 14, blocks, no_row_scaling), PERM_EHIP.
  */
@@ -255,7 +258,8 @@ perm_status perm_sparse(int dtype, const void* dA, int n, int ld, int trials, ui
  * perm_sparse_partial -- the raw sum of Eq. ryser's terms (-1)^|J| prod_i sum_{j in J}
  * a_ij over Gray indices [start, start + count) of that enumeration, without the
  * factor (-1)^n; start + count <= out->terms of perm_sparse.  0/1 input gives the
- * FP64 double-double sum (no exactness check).  Arguments as perm_sparse.
+ * exact integer sum modulo 2^128 in int_lo/int_hi (no range check).  Arguments as
+ * perm_sparse.
  */
 perm_status perm_sparse_partial(int dtype, const void* dA, int n, int ld, int trials,
                                 uint64_t seed, uint64_t start, uint64_t count,

@@ -315,7 +315,7 @@ def perm_sparse_partial(A, start: int, count: int, trials: int = 1, seed: int = 
     _check(_lib.perm_sparse_partial(dt, p, n, ld, int(trials), int(seed), int(start), int(count),
                                     ctypes.byref(o), ctypes.byref(r), _stream_handle(stream)),
            "perm_sparse_partial")
-    return _result(r, False)
+    return _result(r, dt == PERM_DT_INT01)
 
 
 def perm_sparse_partition(A, trials: int = 1, seed: int = 0, stream=None):

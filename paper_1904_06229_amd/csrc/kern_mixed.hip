@@ -17,7 +17,17 @@
 //
 // Per term: n FP64 additions (complex 2n), the product of the row sums, one
 // multiply by the inner weight, and a double-double lane sum per pair of terms.
+//
+// Exact variant (0/1 data of the sparse enumeration, whose digit weights are
+// all +-1): the row sums are integers, every product is formed exactly in
+// row groups and entered into 51-bit integer bins (perm_exact.hpp), and a
+// chunk's bins fold into a 128-bit integer.  There the signs alternate from
+// step to step, so a pair of terms enters as P_s - P_{s+1} and the chunk sum
+// is multiplied by the sign of its first term at the end.
 #include "perm_device.hpp"
+#if !PERM_CPLX
+#include "perm_exact.hpp"
+#endif
 
 namespace perm {
 namespace {
@@ -78,32 +88,33 @@ __device__ __forceinline__ void product(const Rows<N>& w, double& pr, double& pi
 #endif
 }
 
-// Digits k = k0 .. R-1 of q (q = chunk index with k0 = b, or term index with
-// k0 = 0): f_k = a_k or r_k - 1 - a_k by the parity of the digits above (a_k
-// the counting digit); adds the digit value's columns to the row sums and
-// multiplies the weight by omega_k(f_k).
+typedef const __attribute__((address_space(4))) uint64_t* cu64ptr;
+
+// Columns c0 .. ncols-1 of the term with Gray index g (c0 = 0: all digits;
+// c0 = the first column of digit b: the outer digits of a chunk starting at
+// g): f_k = a_k or r_k - 1 - a_k by the parity of floor(g / Q_{k+1}) (a_k the
+// counting digit), then each column adds its coefficient times itself to the
+// row sums (kind 0: f copies; kind 1: bit e of gray(f + 1)) and the digit's
+// first column multiplies the weight by omega_k(f_k).  One flat loop over
+// columns keeps a single copy of the row sums live.
 template <int N>
-__device__ __forceinline__ void outer_digits(const MixArgs& a, const double* staged, uint64_t q,
-                                             int k0, Rows<N>& w, double& W) {
+__device__ __forceinline__ void outer_digits(const MixArgs& a, const double* staged, uint64_t g,
+                                             int c0, Rows<N>& w, double& W) {
   ciptr dig = (ciptr)a.dig;
+  cu64ptr qabs = (cu64ptr)a.qabs;
 #pragma unroll 1
-  for (int k = k0; k < a.R; ++k) {
+  for (int c = c0; c < a.ncols; ++c) {
+    const int k = dig[kDigColDigit * kMaxN + c];
+    const int e = dig[kDigColBit * kMaxN + c];
     const uint32_t r = (uint32_t)dig[kDigRadix * kMaxN + k];
-    const int kind = dig[kDigKind * kMaxN + k];
-    const int first = dig[kDigFirst * kMaxN + k];
-    const uint64_t qn = q / r;
-    const uint32_t dgt = (uint32_t)(q - qn * r);
-    q = qn;
-    const uint32_t f = (q & 1) ? r - 1u - dgt : dgt;
-    W *= a.omega[dig[kDigWofs * kMaxN + k] + f];
-    if (kind == 0) {
-      add_col_times<N>(w, staged, first, (double)f);
-    } else {
-      const uint32_t sub = (f + 1u) ^ ((f + 1u) >> 1);
-      const int size = dig[kDigSize * kMaxN + k];
-#pragma unroll 1
-      for (int e = 0; e < size; ++e) add_col_times<N>(w, staged, first + e, (double)((sub >> e) & 1u));
-    }
+    const uint64_t x = g / qabs[k];
+    const uint64_t hi = x / r;
+    const uint32_t dgt = (uint32_t)(x - hi * r);
+    const uint32_t f = (hi & 1) ? r - 1u - dgt : dgt;
+    if (e == 0) W *= a.omega[dig[kDigWofs * kMaxN + k] + f];
+    const uint32_t sub = (f + 1u) ^ ((f + 1u) >> 1);
+    const double coef = dig[kDigKind * kMaxN + k] == 0 ? (double)f : (double)((sub >> e) & 1u);
+    add_col_times<N>(w, staged, c, coef);
   }
 }
 
@@ -148,7 +159,7 @@ __device__ __forceinline__ Acc walk_chunk(const MixArgs& a, uint64_t c, uint32_t
     }
   }
   double W = 1.0;
-  outer_digits<N>(a, staged, c, a.b, w, W);
+  outer_digits<N>(a, staged, c * (uint64_t)a.L, a.outer_col, w, W);
   cdptr tin = as_const(a.tin + par * (uint32_t)a.L);
   ciptr toff = (ciptr)(a.toff + par * (uint32_t)a.L);
   Acc acc{{0.0, 0.0}, {0.0, 0.0}};
@@ -160,8 +171,12 @@ __device__ __forceinline__ Acc walk_chunk(const MixArgs& a, uint64_t c, uint32_t
     double p0r, p0i, p1r, p1i;
     product<N>(w, p0r, p0i);
     add_col<N>(w, staged, o0);
+    // keep the next column's scalar loads behind this one's adds: two columns
+    // in SGPRs at once would spill
+    __builtin_amdgcn_sched_barrier(0);
     product<N>(w, p1r, p1i);
     add_col<N>(w, staged, o1);
+    __builtin_amdgcn_sched_barrier(0);
     dd_acc(acc.re, fma(t1, p1r, t0 * p0r));
 #if PERM_CPLX
     dd_acc(acc.im, fma(t1, p1i, t0 * p0i));
@@ -177,6 +192,100 @@ __device__ __forceinline__ Acc walk_chunk(const MixArgs& a, uint64_t c, uint32_t
   }
   return Acc{dd_scale(acc.re, W), dd_scale(acc.im, W)};
 }
+
+#if !PERM_CPLX
+__device__ __forceinline__ u128 u128_neg(u128 v) {
+  const uint64_t lo = ~v.lo + 1u;
+  return u128{lo, ~v.hi + (lo == 0 ? 1u : 0u)};
+}
+
+// Exact integer form of the single term g.
+template <int N>
+__device__ __forceinline__ u128 exact_single(const MixArgs& a, uint64_t g) {
+  const double* staged = opaque(a.staged);
+  Rows<N> w;
+#pragma unroll
+  for (int i = 0; i < N; ++i) w.r[i] = 0.0;
+  double W = 1.0;
+  outer_digits<N>(a, staged, g, 0, w, W);
+  exact::Bins B{0, 0, 0};
+  const exact::Bins off = exact::term_offsets<N>();
+  if (W > 0.0) {
+    exact::term_bins<N, true>(w.r, B);
+    B.b0 -= off.b0;
+    B.b1 -= off.b1;
+    B.b2 -= off.b2;
+  } else {
+    exact::term_bins<N, false>(w.r, B);
+    B.b0 += off.b0;
+    B.b1 += off.b1;
+    B.b2 += off.b2;
+  }
+  return exact::fold(B);
+}
+
+// Exact integer sum of chunk c (L <= 2^10 terms, weights +-1 alternating).
+template <int N>
+__device__ __forceinline__ u128 exact_chunk(const MixArgs& a, uint64_t c, uint32_t par) {
+  const double* staged = opaque(a.staged);
+  Rows<N> w;
+  {
+    cdptr st = as_const(staged + (2 * (a.ncols + 1) + (int)par) * N);
+#pragma unroll
+    for (int i = 0; i < N; ++i) w.r[i] = st[i];
+  }
+  double W = 1.0;
+  outer_digits<N>(a, staged, c * (uint64_t)a.L, a.outer_col, w, W);
+  cdptr tin = as_const(a.tin + par * (uint32_t)a.L);
+  ciptr toff = (ciptr)(a.toff + par * (uint32_t)a.L);
+  exact::Bins B{0, 0, 0};
+  const int L = a.L;
+  int s = 0;
+  for (; s + 1 < L; s += 2) {
+    const int32_t o0 = toff[s], o1 = toff[s + 1];
+    exact::term_bins<N, true>(w.r, B);   // + P_s
+    add_col<N>(w, staged, o0);
+    exact::term_bins<N, false>(w.r, B);  // - P_{s+1}
+    add_col<N>(w, staged, o1);
+  }
+  if (s < L) {  // odd L: an unpaired + P_{L-1}
+    exact::term_bins<N, true>(w.r, B);
+    const exact::Bins off = exact::term_offsets<N>();
+    B.b0 -= off.b0;
+    B.b1 -= off.b1;
+    B.b2 -= off.b2;
+  }
+  const u128 v = exact::fold(B);  // sum_s (-1)^s P_s
+  return ((tin[0] < 0.0) != (W < 0.0)) ? u128_neg(v) : v;
+}
+
+template <int N, bool SINGLE>
+__global__ __launch_bounds__(kBlock) void mix_exact_kernel(MixArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint64_t wave = wave_id();
+  const uint64_t nwaves = (uint64_t)gridDim.x * kWavesPerBlock;
+  u128 acc{0, 0};
+  if (a.status[0] == kStOk) {
+    for (uint64_t task = wave; task < a.ntasks; task += nwaves) {
+      const uint64_t c = task_chunk(task, lane);
+      u128 part;
+      if constexpr (SINGLE) {
+        part = exact_single<N>(a, a.first + c);
+      } else {
+        const uint32_t par = (uint32_t)((a.first + (task & 1)) & 1);
+        part = exact_chunk<N>(a, a.first + c, par);
+      }
+      if (c < a.nchunks) acc = u128_add(acc, part);
+    }
+  }
+  const u128 bs = block_sum(wave_sum(acc), u128_add);
+  if (threadIdx.x == 0) {
+    uint64_t* out = (uint64_t*)a.partials;
+    out[2 * blockIdx.x] = bs.lo;
+    out[2 * blockIdx.x + 1] = bs.hi;
+  }
+}
+#endif
 
 template <int N, bool SINGLE>
 __global__ __launch_bounds__(kBlock) void mix_walk_kernel(MixArgs a) {
@@ -223,7 +332,18 @@ __global__ __launch_bounds__(kBlock) void mix_walk_kernel(MixArgs a) {
 }
 
 template <int N>
-hipError_t dispatch(bool single, const MixArgs& a, int grid, hipStream_t s) {
+hipError_t dispatch(bool single, bool exact, const MixArgs& a, int grid, hipStream_t s) {
+  if (exact) {
+#if PERM_CPLX
+    return hipErrorInvalidValue;
+#else
+    if (single)
+      hipLaunchKernelGGL((mix_exact_kernel<N, true>), dim3(grid), dim3(kBlock), 0, s, a);
+    else
+      hipLaunchKernelGGL((mix_exact_kernel<N, false>), dim3(grid), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+#endif
+  }
   if (single)
     hipLaunchKernelGGL((mix_walk_kernel<N, true>), dim3(grid), dim3(kBlock), 0, s, a);
   else
@@ -235,7 +355,7 @@ hipError_t dispatch(bool single, const MixArgs& a, int grid, hipStream_t s) {
 
 #define PERM_CASE(N) \
   case N:            \
-    return dispatch<N>(single, a, grid, s);
+    return dispatch<N>(single, exact, a, grid, s);
 
 // Built four times: PERM_CPLX selects real or complex, PERM_HALF the sizes
 // n = 1..32 or n = 33..64.
@@ -258,7 +378,8 @@ hipError_t dispatch(bool single, const MixArgs& a, int grid, hipStream_t s) {
 #define PERM_CASES "perm_cases_hi.inc"
 #endif
 
-hipError_t PERM_LAUNCH(int n, bool single, const MixArgs& a, int grid, hipStream_t s) {
+hipError_t PERM_LAUNCH(int n, bool single, bool exact, const MixArgs& a, int grid,
+                       hipStream_t s) {
   switch (n) {
 #include PERM_CASES
     default:

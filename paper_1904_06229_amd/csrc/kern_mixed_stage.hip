@@ -8,7 +8,8 @@
 //            ld = n), then the two start columns (chunk parity 0, 1): the row
 //            sums of the inner digits' values at the first step of a chunk
 //   omega  : the signed weight of every value of every digit
-//   dig    : radix, kind, first staged column, size and omega offset per digit
+//   dig    : radix, kind and omega offset per digit; digit and bit per column
+//   qabs   : Q_k = r_0 ... r_{k-1} for k = 0..R
 //   tin    : signed weight of the inner digits at step s of a chunk of parity
 //            0 or 1
 //   toff   : offset of the column added after step s (+c or -c; the zero
@@ -49,7 +50,8 @@ __global__ __launch_bounds__(kBlock) void stage_mix_kernel(const void* __restric
                                                            int L, int row_scaling, double* staged,
                                                            double* omega, double* tin,
                                                            int32_t* toff, int32_t* dig,
-                                                           int32_t* rowexp, int32_t* status) {
+                                                           uint64_t* qabs, int32_t* rowexp,
+                                                           int32_t* status) {
   __shared__ uint64_t s_pascal[kMaxN + 1][kMaxN + 1];
   __shared__ int32_t s_exp[kMaxN], s_wofs[kMaxN], s_r[kMaxN];
   __shared__ uint32_t s_Q[kMaxN + 1];
@@ -125,9 +127,19 @@ __global__ __launch_bounds__(kBlock) void stage_mix_kernel(const void* __restric
   if (tid < R) {
     dig[kDigRadix * kMaxN + tid] = dg.radix[tid];
     dig[kDigKind * kMaxN + tid] = dg.kind[tid];
-    dig[kDigFirst * kMaxN + tid] = dg.first[tid];
-    dig[kDigSize * kMaxN + tid] = dg.size[tid];
     dig[kDigWofs * kMaxN + tid] = s_wofs[tid];
+    for (int e = 0; e < dg.size[tid]; ++e) {
+      dig[kDigColDigit * kMaxN + dg.first[tid] + e] = tid;
+      dig[kDigColBit * kMaxN + dg.first[tid] + e] = e;
+    }
+  }
+  if (tid == 0) {
+    uint64_t q = 1;  // the product of all radices is at most 2^63
+    for (int k = 0; k < R; ++k) {
+      qabs[k] = q;
+      q *= (uint64_t)dg.radix[k];
+    }
+    qabs[R] = q;
   }
   // inner-digit tables
   const uint32_t uL = (uint32_t)L;
@@ -186,7 +198,11 @@ __global__ __launch_bounds__(kBlock) void stage_mix_kernel(const void* __restric
     staged[o] = sr;
     if (cw == 2) staged[o + 1] = si;
   }
-  if (tid == 0) status[0] = s_bad ? kStNonFinite : kStOk;
+  if (tid == 0) {
+    status[0] = s_bad ? kStNonFinite : kStOk;
+    status[1] = 0;
+    status[2] = 0;
+  }
 }
 
 // splitmix64 (Steele, Lea and Flood, 2014): a counter-based 64-bit hash.
@@ -265,10 +281,16 @@ __global__ __launch_bounds__(kBlock) void sparse_partition_kernel(const void* __
   __syncthreads();
   if (tid == 0) {
     int zero = 0;
-    double ldp = 0.0;
+    double ldp = 0.0, breg = 0.0;
     for (int i = 0; i < n; ++i) {
-      if (s_deg[i] == 0) zero = 1;
-      else ldp += log2((double)s_deg[i]);
+      if (s_deg[i] == 0) {
+        zero = 1;
+      } else {
+        ldp += log2((double)s_deg[i]);
+        double lf = 0.0;
+        for (int q = 2; q <= s_deg[i]; ++q) lf += log2((double)q);
+        breg += lf / s_deg[i];
+      }
     }
     int best = 0;
     for (int t = 1; t < trials; ++t)
@@ -294,6 +316,7 @@ __global__ __launch_bounds__(kBlock) void sparse_partition_kernel(const void* __
     out->trial = best;
     out->log2_terms = s_score[best];
     out->log2_degprod = ldp;
+    out->bregman = breg;
   }
 }
 
@@ -301,10 +324,10 @@ __global__ __launch_bounds__(kBlock) void sparse_partition_kernel(const void* __
 
 hipError_t launch_mix_stage(int in_kind, const void* A, int n, int ld, const MixDigits& dg,
                             int b, int L, int row_scaling, double* staged, double* omega,
-                            double* tin, int32_t* toff, int32_t* dig, int32_t* rowexp,
-                            int32_t* status, hipStream_t s) {
+                            double* tin, int32_t* toff, int32_t* dig, uint64_t* qabs,
+                            int32_t* rowexp, int32_t* status, hipStream_t s) {
   hipLaunchKernelGGL(stage_mix_kernel, dim3(1), dim3(kBlock), 0, s, A, in_kind, n, ld, dg, b, L,
-                     row_scaling, staged, omega, tin, toff, dig, rowexp, status);
+                     row_scaling, staged, omega, tin, toff, dig, qabs, rowexp, status);
   return hipGetLastError();
 }
 

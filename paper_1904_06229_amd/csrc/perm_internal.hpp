@@ -153,8 +153,10 @@ struct MixDigits {
   int32_t cmult[kMaxN];   // copies of staged column c in the matrix (row-norm weight)
 };
 
-// Device copy of the digit description, read with scalar loads by the walk.
-enum { kDigRadix = 0, kDigKind = 1, kDigFirst = 2, kDigSize = 3, kDigWofs = 4, kDigFields = 5 };
+// Device copy of the digit description, read with scalar loads by the walk:
+// per digit its radix, kind and omega offset; per staged column the digit it
+// belongs to and its bit within the digit's subset (0 for kind 0).
+enum { kDigRadix = 0, kDigKind = 1, kDigWofs = 2, kDigColDigit = 3, kDigColBit = 4, kDigFields = 5 };
 
 struct MixArgs {
   const double* staged;   // [+cols | 0] [-cols | 0] (n x (ncols+1) each), then two start columns
@@ -163,25 +165,33 @@ struct MixArgs {
   const int32_t* toff;    // 2 x L: offset (doubles) into staged of the column added after
                           // step s; the last step adds the zero column
   const int32_t* dig;     // kDigFields x kMaxN digit fields
+  const uint64_t* qabs;   // Q_k = r_0 ... r_{k-1}, k = 0..R
   const int32_t* status;  // staging status; nonzero -> the walk does nothing
   uint64_t first;         // first chunk (walk) or first Gray index (single terms)
   uint64_t nchunks;
   uint64_t ntasks;        // 2 * ceil(nchunks / 128)
   int32_t R, b, L, ncols;
+  int32_t outer_col;      // first staged column of digit b (the first outer digit)
+  int32_t pad;
   void* partials;         // per workgroup: dd (real) or complex dd
 };
 
 // in_kind: 0 real doubles, 1 complex pairs, 2 bytes (0/1 data, staged as doubles).
 hipError_t launch_mix_stage(int in_kind, const void* A, int n, int ld, const MixDigits& dg,
                             int b, int L, int row_scaling, double* staged, double* omega,
-                            double* tin, int32_t* toff, int32_t* dig, int32_t* rowexp,
-                            int32_t* status, hipStream_t s);
+                            double* tin, int32_t* toff, int32_t* dig, uint64_t* qabs,
+                            int32_t* rowexp, int32_t* status, hipStream_t s);
 // single: every lane sums one term (Gray indices first .. first + nchunks - 1).
-hipError_t launch_mix_walk_real_lo(int n, bool single, const MixArgs& a, int grid, hipStream_t s);
-hipError_t launch_mix_walk_real_hi(int n, bool single, const MixArgs& a, int grid, hipStream_t s);
-hipError_t launch_mix_walk_complex_lo(int n, bool single, const MixArgs& a, int grid,
+// exact (real only; 0/1 data with weights +-1, L <= 2^10): 128-bit integer
+// partials instead of double-double ones.
+constexpr int kMixExactMaxLog2Chunk = 10;
+hipError_t launch_mix_walk_real_lo(int n, bool single, bool exact, const MixArgs& a, int grid,
+                                   hipStream_t s);
+hipError_t launch_mix_walk_real_hi(int n, bool single, bool exact, const MixArgs& a, int grid,
+                                   hipStream_t s);
+hipError_t launch_mix_walk_complex_lo(int n, bool single, bool exact, const MixArgs& a, int grid,
                                       hipStream_t s);
-hipError_t launch_mix_walk_complex_hi(int n, bool single, const MixArgs& a, int grid,
+hipError_t launch_mix_walk_complex_hi(int n, bool single, bool exact, const MixArgs& a, int grid,
                                       hipStream_t s);
 
 // App. B greedypartition on the device.  Trial 0 takes the lowest row index
@@ -197,6 +207,7 @@ struct SparsePart {
   int32_t bsize[kMaxN];
   double log2_terms;      // log2 of 2^|T| prod (2^|S| - 1)
   double log2_degprod;    // log2 prod_i (nonzeros of row i)
+  double bregman;         // sum_i log2(d_i!) / d_i: log2 of Bregman's bound on |per| (0/1 data)
 };
 
 hipError_t launch_sparse_partition(int in_kind, const void* A, int n, int ld, int trials,

@@ -38,6 +38,7 @@ struct MixWorkspace {
   int32_t* status = nullptr;
   int32_t* rowexp = nullptr;
   int32_t* dig = nullptr;
+  uint64_t* qabs = nullptr;
   DevResult* dres = nullptr;
   SparsePart* dpart = nullptr;
   double* staged = nullptr;
@@ -81,6 +82,7 @@ perm_status get_ws(MixWorkspace** out) {
   const size_t o_status = take(64);
   const size_t o_rowexp = take(sizeof(int32_t) * kMaxN);
   const size_t o_dig = take(sizeof(int32_t) * kDigFields * kMaxN);
+  const size_t o_qabs = take(sizeof(uint64_t) * (kMaxN + 1));
   const size_t o_res = take(sizeof(DevResult));
   const size_t o_part = take(sizeof(SparsePart));
   const size_t o_staged = take(sizeof(double) * 2 * (2 * (kMaxN + 1) + 2) * kMaxN);
@@ -108,6 +110,7 @@ perm_status get_ws(MixWorkspace** out) {
   w->status = (int32_t*)(w->dmem + o_status);
   w->rowexp = (int32_t*)(w->dmem + o_rowexp);
   w->dig = (int32_t*)(w->dmem + o_dig);
+  w->qabs = (uint64_t*)(w->dmem + o_qabs);
   w->dres = (DevResult*)(w->dmem + o_res);
   w->dpart = (SparsePart*)(w->dmem + o_part);
   w->staged = (double*)(w->dmem + o_staged);
@@ -122,12 +125,13 @@ perm_status get_ws(MixWorkspace** out) {
 
 int floor_log2(uint64_t x) { return x ? 63 - __builtin_clzll(x) : -1; }
 
-hipError_t launch_walk(bool cplx, int n, bool single, const MixArgs& a, int grid, hipStream_t s) {
+hipError_t launch_walk(bool cplx, int n, bool single, bool exact, const MixArgs& a, int grid,
+                       hipStream_t s) {
   if (cplx)
-    return n <= 32 ? launch_mix_walk_complex_lo(n, single, a, grid, s)
-                   : launch_mix_walk_complex_hi(n, single, a, grid, s);
-  return n <= 32 ? launch_mix_walk_real_lo(n, single, a, grid, s)
-                 : launch_mix_walk_real_hi(n, single, a, grid, s);
+    return n <= 32 ? launch_mix_walk_complex_lo(n, single, exact, a, grid, s)
+                   : launch_mix_walk_complex_hi(n, single, exact, a, grid, s);
+  return n <= 32 ? launch_mix_walk_real_lo(n, single, exact, a, grid, s)
+                 : launch_mix_walk_real_hi(n, single, exact, a, grid, s);
 }
 
 // The options the mixed-radix walks take: precision PERM_FP64_DD, log2_chunk
@@ -153,9 +157,10 @@ struct Walked {
 };
 
 // Stage and walk Gray indices [start, start + count) of the digit order.
+// exact: 128-bit integer sums (0/1 data, weights +-1).
 perm_status run_mixed(MixWorkspace* ws, int in_kind, const void* dA, int n, int ld,
                       const MixDigits& dg, uint64_t start, uint64_t count, const perm_opts& o,
-                      int row_scaling, hipStream_t stream, Walked* wk) {
+                      int row_scaling, bool exact, hipStream_t stream, Walked* wk) {
   const bool cplx = in_kind == 1;
   // Inner digits: as many leading digits as fit in the chunk cap (at least one).
   int cap_lg = o.log2_chunk;
@@ -163,6 +168,7 @@ perm_status run_mixed(MixWorkspace* ws, int in_kind, const void* dA, int n, int 
     cap_lg = floor_log2(count) - 18;
     cap_lg = cap_lg < 4 ? 4 : (cap_lg > 12 ? 12 : cap_lg);
   }
+  if (exact && cap_lg > kMixExactMaxLog2Chunk) cap_lg = kMixExactMaxLog2Chunk;
   const uint64_t cap = 1ull << cap_lg;
   int b = 0;
   uint64_t L = 1;
@@ -178,9 +184,10 @@ perm_status run_mixed(MixWorkspace* ws, int in_kind, const void* dA, int n, int 
   const int grid_cap = o.blocks > 0 ? o.blocks : 8 * ws->cu_count;
   MIX_TRY(hipEventRecord(ws->ev[0], stream));
   MIX_TRY(launch_mix_stage(in_kind, dA, n, ld, dg, b, (int)L, row_scaling, ws->staged, ws->omega,
-                           ws->tin, ws->toff, ws->dig, ws->rowexp, ws->status, stream));
+                           ws->tin, ws->toff, ws->dig, ws->qabs, ws->rowexp, ws->status,
+                           stream));
   int nparts = 0, body_grid = 0;
-  const size_t part_bytes = cplx ? 32 : 16;
+  const size_t part_bytes = (cplx && !exact) ? 32 : 16;
   auto walk = [&](uint64_t first, uint64_t nchunks, bool single, int* grid_out) -> perm_status {
     if (nchunks == 0) return PERM_OK;
     MixArgs a;
@@ -189,6 +196,7 @@ perm_status run_mixed(MixWorkspace* ws, int in_kind, const void* dA, int n, int 
     a.tin = ws->tin;
     a.toff = ws->toff;
     a.dig = ws->dig;
+    a.qabs = ws->qabs;
     a.status = ws->status;
     a.first = first;
     a.nchunks = nchunks;
@@ -197,6 +205,8 @@ perm_status run_mixed(MixWorkspace* ws, int in_kind, const void* dA, int n, int 
     a.b = b;
     a.L = (int32_t)L;
     a.ncols = dg.ncols;
+    a.outer_col = b < dg.R ? dg.first[b] : dg.ncols;
+    a.pad = 0;
     a.partials = (char*)ws->partials + part_bytes * nparts;
     uint64_t blocks = (a.ntasks + kWavesPerBlock - 1) / kWavesPerBlock;
     if (blocks > (uint64_t)grid_cap) blocks = (uint64_t)grid_cap;
@@ -204,7 +214,7 @@ perm_status run_mixed(MixWorkspace* ws, int in_kind, const void* dA, int n, int 
     const int grid = (int)blocks;
     if (grid_out) *grid_out = grid;
     nparts += grid;
-    const hipError_t e = launch_walk(cplx, n, single, a, grid, stream);
+    const hipError_t e = launch_walk(cplx, n, single, exact, a, grid, stream);
     if (e != hipSuccess) return hip_fail("mixed-radix walk launch", e);
     return PERM_OK;
   };
@@ -214,8 +224,8 @@ perm_status run_mixed(MixWorkspace* ws, int in_kind, const void* dA, int n, int 
   if ((st = walk(a0 / L, (a1 - a0) / L, false, &body_grid)) != PERM_OK) return st;
   if ((st = walk(a1, end - a1, true, nullptr)) != PERM_OK) return st;
   MIX_TRY(hipEventRecord(ws->ev[2], stream));
-  MIX_TRY(launch_finish(cplx ? kComplex : kReal, ws->partials, nparts, nullptr, 0, ws->status,
-                        ws->rowexp, n, nullptr, ws->dres, stream));
+  MIX_TRY(launch_finish(exact ? kInt01 : (cplx ? kComplex : kReal), ws->partials, nparts,
+                        nullptr, 0, ws->status, ws->rowexp, n, nullptr, ws->dres, stream));
   MIX_TRY(hipMemcpyAsync(ws->hres, ws->dres, sizeof(DevResult), hipMemcpyDeviceToHost, stream));
   MIX_TRY(hipEventRecord(ws->ev[3], stream));
   MIX_TRY(hipStreamSynchronize(stream));
@@ -309,7 +319,7 @@ perm_status rep_call(int dtype, const double* dC, int n, int R, int ld, const in
   if ((st = get_ws(&ws)) != PERM_OK) return st;
   Walked wk;
   st = run_mixed(ws, dtype == PERM_DT_COMPLEX ? 1 : 0, dC, n, ld, dg, start, count, o,
-                 o.no_row_scaling ? 0 : 1, stream, &wk);
+                 o.no_row_scaling ? 0 : 1, false, stream, &wk);
   if (st != PERM_OK) return st;
   fill_float(wk, (whole && (n % 2)) ? -1.0 : 1.0, count, &r);  // per = (-1)^n S
   *out = r;
@@ -397,24 +407,28 @@ perm_status sparse_call(int dtype, const void* dA, int n, int ld, int trials, ui
   }
   if (start > T || count > T - start) return set_error(PERM_EINVAL, "range outside [0, terms)");
   const bool exact = dtype == PERM_DT_INT01;
-  if (exact && whole && !(p.log2_degprod < 52.0 && std::log2((double)T) + p.log2_degprod <= 100.0))
-    return set_error(PERM_ERANGE,
-                     "0/1 sparse path: products or sums may exceed the exact FP64 range");
+  if (exact && whole && p.bregman >= 127.0)
+    return set_error(PERM_ERANGE, "exact 0/1 result may exceed 128 bits (Bregman bound >= 127)");
   if (count == 0) {
     *out = r;
     return PERM_OK;
   }
   Walked wk;
   st = run_mixed(ws, in_kind_of(dtype), dA, n, ld, dg, start, count, o,
-                 (exact || o.no_row_scaling) ? 0 : 1, stream, &wk);
+                 (exact || o.no_row_scaling) ? 0 : 1, exact, stream, &wk);
   if (st != PERM_OK) return st;
   fill_float(wk, (whole && (n % 2)) ? -1.0 : 1.0, count, &r);
-  if (exact && whole) {
-    // integer row sums, products below 2^52 and a sum below 2^100: hi and lo
-    // are integers and hi + lo is the permanent
-    const __int128 v = (__int128)r.re_hi + (__int128)r.re_lo;
-    r.int_lo = (uint64_t)(unsigned __int128)v;
-    r.int_hi = (int64_t)(v >> 64);
+  if (exact) {
+    // S = sum over the sets of (-1)^|J| prod_i r_i modulo 2^128; per = (-1)^n S
+    unsigned __int128 u = ((unsigned __int128)wk.res.iw[1] << 64) | wk.res.iw[0];
+    if (whole && (n % 2)) u = (unsigned __int128)0 - u;
+    const __int128 v = (__int128)u;
+    r.int_lo = (uint64_t)u;
+    r.int_hi = (int64_t)(u >> 64);
+    const double h = (double)v;
+    r.re_hi = h;
+    r.re_lo = std::fabs(h) >= 1.7014118346046923e38 ? 0.0 : (double)(v - (__int128)h);
+    r.im_hi = r.im_lo = 0.0;
   }
   *out = r;
   return PERM_OK;

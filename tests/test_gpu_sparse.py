@@ -94,6 +94,28 @@ def test_int01_exact(B, orc, n, p):
     assert got.exact == want and got.terms == terms
 
 
+@pytest.mark.parametrize("n,p,seed", [(20, 0.4, 1), (24, 0.35, 2), (26, 0.5, 3), (28, 0.3, 4)])
+def test_int01_exact_beyond_fp64_products(B, orc, n, p, seed):
+    """Row degrees whose product is far above 2^53: the exact variant (integer
+    bins) still gives the permanent bit for bit."""
+    A = sparse_matrix(n, p, seed, "int")
+    assert np.log2(A.sum(axis=1)).sum() > 60
+    got = B.perm_sparse(dev(A))
+    want = orc.ryser(A)
+    log(f"0/1 n={n} p={p}: per {want}, {got.terms} sets, log2 prod deg "
+        f"{np.log2(A.sum(axis=1)).sum():.0f}")
+    assert got.exact == want
+
+
+def test_int01_all_ones_and_range_guard(B):
+    from paper_1904_06229_amd import inputs
+    J = inputs.ones(30)  # one block of 30 columns is too large to restrict: 2^30 sets
+    assert B.perm_sparse(dev(J)).exact == math.factorial(30)
+    with pytest.raises(B.PermError) as e:
+        B.perm_sparse(dev(inputs.ones(40)))  # Bregman: log2(40!) = 159 >= 127
+    assert e.value.status == B.PERM_ERANGE
+
+
 def test_int01_band_shaped_n64_against_band_oracle(B, orc):
     """n = 64: a sparse matrix inside a band of half-width 3 (zeros at random
     in the band, ones on the diagonal) has an exact value from the App. C
@@ -151,6 +173,7 @@ def test_int01_partial_sums_exact(B, orc):
     for start, count in ((0, T), (3, T // 3), (T // 2, T - T // 2)):
         got = B.perm_sparse_partial(dev(A), start, count)
         want = orc.sparse_range(A, start, count)
+        assert got.exact == int(want.exact), (start, count)
         assert got.re_hi + got.re_lo == float(want.exact), (start, count)
 
 
