@@ -16,7 +16,8 @@ Other workloads (--workload c1|c3|c5|c4|c6) are for manual runs; c5 (48x48
 real, 2^47 terms, minutes per permanent) runs as 16 perm_partial slices with
 a progress line each; c6 is the repeated-column path (Eq. ryser2) on a
 48-photon output with two photons in each of 24 modes; c7 is the band
-transfer matrix (App. C) on a batch of 64 x 64 band matrices.
+transfer matrix (App. C) on a batch of 64 x 64 band matrices; c8 the exact
+sparse path (App. B) on the paper's identity + Bernoulli(p) matrices.
 """
 from __future__ import annotations
 
@@ -54,7 +55,7 @@ def algorithmic_ops_per_term(kind: str, n: int, col0_nonzeros: int = 0) -> float
 
 
 KERNEL_SOURCES = {
-    "int01": ["kern_int01.hip"],
+    "int01": ["kern_int01.hip", "perm_exact.hpp"],
     "real": ["kern_real.hip", "perm_walk.hpp"],
     "complex": ["kern_complex.hip", "perm_walk.hpp"],
 }
@@ -95,7 +96,7 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="c2",
-                   choices=["c1", "c2", "c3", "c4", "c5", "c6", "c7"])
+                   choices=["c1", "c2", "c3", "c4", "c5", "c6", "c7", "c8"])
     p.add_argument("--count", type=int, default=100000, help="c4: number of matrices")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--blocks", type=int, default=0)
@@ -413,6 +414,70 @@ def bench_band(args):
     print(json.dumps(o))
 
 
+def bench_sparse(args):
+    """The sparse matrices of the paper's timing study (Sec. II.D): ones on the
+    diagonal, other entries 1 with probability p; n = 64, p = 0.02, exact
+    0/1 result by App. B's restricted Ryser sum (64 greedy partition trials)."""
+    import numpy as np
+    import torch
+    from paper_1904_06229_amd import binding as B
+
+    n, p, seed, trials = 64, 0.02, 20190408, 64
+    r = np.random.default_rng(seed)
+    M = r.random((n, n)) < p
+    np.fill_diagonal(M, True)
+    A = M.astype(np.uint8)
+    dA = torch.from_numpy(np.asfortranarray(A)).to("cuda")
+    blk, nblocks, T = B.perm_sparse_partition(dA, trials=trials, seed=1)
+    for _ in range(args.warmup):
+        res = B.perm_sparse(dA, trials=trials, seed=1, blocks=args.blocks)
+    torch.cuda.synchronize()
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = B.perm_sparse(dA, trials=trials, seed=1, blocks=args.blocks)
+        kms.append(res.kernel_ms)
+    dt = time.perf_counter() - t0
+    kavg = sum(kms) / len(kms)
+    alg = algorithmic_ops_per_term("real", n) * float(T)  # n updates + n-1 products + 1
+    out = {
+        "metric": "sparse column sets/sec (n*sets/s)",
+        "value": args.steps * n * float(T) / dt, "unit": "n*sets/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64-held integers + i64 bins (exact)", "data": "synthetic",
+        "config": {"workload": f"64x64 0/1, ones on the diagonal, other entries Bernoulli({p}), "
+                               f"seed {seed}, exact, App. B with {trials} partition trials",
+                   "n": n, "p": p, "sets": T, "blocks_in_partition": nblocks,
+                   "log2_sets": math.log2(T), "inner_digits": res.log2_chunk},
+        "roofline": {"bound": "alu", "achieved": alg / (kavg * 1e-3) / 1e12,
+                     "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
+                     "frac": alg / (kavg * 1e-3) / PEAK_LANE_OPS, "traffic": None,
+                     "kernel": f"mix_exact_kernel<{n}, false>", "kernel_ms": kavg,
+                     "ops_per_launch": alg,
+                     "note": "algorithmic count of the FP64 walk (2n per set); the exact "
+                             "products cost more issue slots"},
+        "result": str(res.exact),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        threads = oracle.default_threads()
+        count = 1 << 12
+        while True:
+            t1 = time.perf_counter()
+            oracle.sparse_range(A, 0, count, threads=threads)
+            cdt = time.perf_counter() - t1
+            if cdt >= 5.0 or count >= T:
+                break
+            count = min(T, count * 2 ** max(1, min(8, int(math.log2(10.0 / max(cdt, 1e-4))))))
+        out["cpu_baseline"] = {"value": n * count / cdt, "unit": "n*sets/s", "cores": threads,
+                               "kind": "oracle", "sample": f"first {count} of the {T} column sets "
+                               "of the Gray enumeration, each term formed directly",
+                               "seconds": round(cdt, 3)}
+    print(json.dumps(out))
+
+
 def bench_sliced(args):
     """Each step is one whole permanent as consecutive perm_partial slices
     (a progress line per slice on stderr); slice sums are added in slice order."""
@@ -483,6 +548,8 @@ def main():
         return bench_repeated(args)
     if args.workload == "c7":
         return bench_band(args)
+    if args.workload == "c8":
+        return bench_sparse(args)
     if args.slices or args.checkpoint or (args.workload == "c5" and not args.terms_log2):
         return bench_sliced(args)
     import numpy as np
