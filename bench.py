@@ -335,16 +335,15 @@ PEAK_LDS_BYTES = 256 * 128 * 2.4e9
 
 
 def band_macs_per_row(k: int) -> int:
-    """Multiply-adds of one interior row of the App. C transfer matrix: for every
-    coefficient mask M after the row and both states of the column that leaves
-    the band, one product per band column present in Q = 2M + b0 (only column
-    i+k when Q holds it)."""
-    top = 2 * k + 1
+    """Multiply-adds of one interior row of the App. C transfer matrix as the
+    kernel computes it: only masks of the surviving class (k+1 of the 2k+1
+    window columns) carry terms; a mask holding column i+k takes one product,
+    any other one product per column it holds."""
+    top = 2 * k
     total = 0
-    for t in range(1 << top):
-        for b0 in (0, 1):
-            q = (t << 1) | b0
-            total += 1 if (q >> top) & 1 else bin(q & (((1 << top) - 1) & ~1)).count("1")
+    for m in range(1 << (2 * k + 1)):
+        if bin(m).count("1") == k + 1:
+            total += 1 if (m >> top) & 1 else k + 1
     return total
 
 

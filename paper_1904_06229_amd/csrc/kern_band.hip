@@ -3,24 +3,34 @@
 //
 // per(A) is the coefficient sum of prod_i C_i, C_i = sum_j a_ij x_j, taken
 // with x_j^2 = 0 (each column used once).  After row i the variable of
-// column i-k-1 is set to 1: no later row reaches that column.  The live
-// polynomial therefore has monomials over the 2k+1 columns [i-k, i+k] only:
-// 2^(2k+1) coefficients, kept in LDS, bit b of a mask standing for column
-// i-k+b.
+// column i-k-1 is set to 1: no later row reaches that column.  The polynomial
+// then lives on the 2k+1 columns [i-k, i+k]; bit b of a mask stands for
+// column i-k+b.
 //
-// One row in gather form: the new coefficient of mask M (window after the
-// row) is the sum over the state of column i-k-1 (bit 0 of Q = 2M + b0, the
-// column dropped by the shift) of P[Q], and P[Q] = sum over the band columns
-// j in Q of old[Q without j] * a_ij.  Column i+k is new in this row, so a Q
-// holding it can only come from j = i+k.  Each thread owns masks t, t+256, ...
-// and reads the old coefficients from the other LDS buffer.
+// Only one popcount class of masks can carry a term that survives to the
+// end.  After row i, rows 0..i have used i+1 columns, and every column below
+// i-k must be among them (no later row reaches it); so a surviving monomial
+// holds exactly p_i = min(i+1, k+1) columns of the window.  A monomial with
+// fewer columns never arises, and one with more has skipped a column for good:
+// all its descendants die by x_j^2 = 0 before the last row (pigeonhole), and
+// it never feeds a mask of the surviving class.  The kernel therefore computes
+// the p_i-class only.  Those coefficients are the same numbers the full
+// polynomial holds (the other classes would only add exact zeros to them),
+// and the final coefficient sum needs only them.
 //
-// One workgroup per matrix (grid-stride over the batch).  Row entries are
-// wave-uniform and read with scalar loads.  Powers of two keep long products
-// in range, exactly: each row's entries are scaled into [1/2, 1), and every
-// 4 rows the coefficients are scaled by the power of two of their largest
-// magnitude (a workgroup max); the exponents are added up and restored at the
-// end.  The final coefficient sum is a fixed-order double-double tree.
+// One row, for a mask M of the new class: with b0 = 1 when column i-k-1
+// exists (it must then be in the term) and Q = 2M + b0 over the columns
+// [i-k-1, i+k], new[M] = sum over the band columns j in Q of old[Q \ j] a_ij.
+// Column i+k is new in this row, so a Q holding it has the single term
+// j = i+k; otherwise the sum runs over the p_i columns of M.  Each lane owns
+// masks of one class (sorted by value, so a wave rarely mixes the two cases)
+// and walks their set bits; the row's band entries sit in LDS.
+//
+// One workgroup per matrix (grid-stride over the batch).  Powers of two keep
+// long products in range, exactly: each row's entries are scaled into
+// [1/2, 1), and every 4 rows the class's coefficients are scaled by the power
+// of two of their largest magnitude; the exponents are restored at the end.
+// The final coefficient sum is a fixed-order double-double tree.
 #include "perm_device.hpp"
 #include "perm_internal.hpp"
 
@@ -29,118 +39,134 @@ namespace {
 
 template <int K, bool CPLX>
 __global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
-  constexpr int S = 1 << (2 * K + 1);   // coefficients after a row
-  constexpr int TOP = 2 * K + 1;        // bit of column i+k in Q
+  constexpr int W = 2 * K + 1;   // window columns
+  constexpr int S = 1 << W;      // masks
+  constexpr int TOP = W;         // bit of column i+k in Q
   constexpr int cw = CPLX ? 2 : 1;
   __shared__ double s_re[2][S];
   __shared__ double s_im[CPLX ? 2 : 1][CPLX ? S : 1];
+  __shared__ uint16_t s_cls[S];          // masks grouped by popcount, ascending in a group
+  __shared__ int32_t s_cls_start[W + 2];
+  __shared__ double s_ar[W + 1], s_ai[CPLX ? W + 1 : 1];
   __shared__ dd s_red[kBlock], s_red_i[CPLX ? kBlock : 1];
   __shared__ double s_mx[kWavesPerBlock];
-  const int tid = threadIdx.x;
   typedef const __attribute__((address_space(4))) int32_t* ci32;
   typedef const __attribute__((address_space(4))) int64_t* ci64;
+  const int tid = threadIdx.x;
+  if (tid == 0) {  // counting sort of the masks by popcount
+    int cnt[W + 2];
+    for (int p = 0; p <= W + 1; ++p) cnt[p] = 0;
+    for (int t = 0; t < S; ++t) ++cnt[__popc(t) + 1];
+    s_cls_start[0] = 0;
+    for (int p = 1; p <= W + 1; ++p) s_cls_start[p] = s_cls_start[p - 1] + cnt[p];
+    for (int p = 0; p <= W; ++p) cnt[p] = s_cls_start[p];
+    for (int t = 0; t < S; ++t) s_cls[cnt[__popc(t)]++] = (uint16_t)t;
+  }
+  __syncthreads();
   for (int m = blockIdx.x; m < a.count; m += gridDim.x) {
     const int n = ((ci32)a.n)[m];  // uniform: scalar loads
     const double* A = a.A + ((ci64)a.off)[m];
-    for (int t = tid; t < S; t += kBlock) {
-      s_re[0][t] = t == 0 ? 1.0 : 0.0;
-      if constexpr (CPLX) s_im[0][t] = 0.0;
+    if (tid == 0) {  // p = 0 class: the empty monomial, coefficient 1
+      s_re[0][0] = 1.0;
+      if constexpr (CPLX) s_im[0][0] = 0.0;
     }
     int cur = 0, esum = 0;
     bool bad = false;
-    __syncthreads();
     for (int i = 0; i < n; ++i) {
-      // band entries of row i: c = 1..2k+1 <-> column j = i-k-1+c
-      double ar[TOP + 1], ai[TOP + 1];
+      // band entries of row i: c = 1..2k+1 <-> column j = i-k-1+c (every
+      // thread reads them, as scalars, for the row's scale)
       double mx = 0.0;
 #pragma unroll
       for (int c = 1; c <= TOP; ++c) {
         const int j = i - K - 1 + c;
         const bool in = j >= 0 && j < n;
         cdptr p = as_const(A + (size_t)cw * ((size_t)i + (size_t)(in ? j : 0) * n));
-        ar[c] = in ? p[0] : 0.0;
-        ai[c] = (CPLX && in) ? p[1] : 0.0;
-        if (!isfinite(ar[c]) || !isfinite(ai[c])) bad = true;
-        mx = fmax(mx, fmax(fabs(ar[c]), fabs(ai[c])));
+        const double vr = in ? p[0] : 0.0;
+        const double vi = (CPLX && in) ? p[1] : 0.0;
+        if (!isfinite(vr) || !isfinite(vi)) bad = true;
+        mx = fmax(mx, fmax(fabs(vr), fabs(vi)));
       }
       int e = 0;
-      if (mx > 0.0 && !bad) {
-        frexp(mx, &e);  // mx in [2^(e-1), 2^e): scale the row by 2^-e
-#pragma unroll
-        for (int c = 1; c <= TOP; ++c) {
-          ar[c] = ldexp(ar[c], -e);
-          ai[c] = ldexp(ai[c], -e);
-        }
-      }
+      if (mx > 0.0 && !bad) frexp(mx, &e);  // scale the row by 2^-e
       esum += e;
+      if (tid >= 1 && tid <= TOP) {
+        const int j = i - K - 1 + tid;
+        const bool in = j >= 0 && j < n;
+        const double* p = A + (size_t)cw * ((size_t)i + (size_t)(in ? j : 0) * n);
+        s_ar[tid] = in ? ldexp(p[0], -e) : 0.0;
+        if constexpr (CPLX) s_ai[tid] = in ? ldexp(p[1], -e) : 0.0;
+      }
+      __syncthreads();
+      const int pcls = i + 1 < K + 1 ? i + 1 : K + 1;
+      const int b0 = (i - K - 1 >= 0) ? 1 : 0;
+      const int c0 = s_cls_start[pcls], c1 = s_cls_start[pcls + 1];
       const double* ore = s_re[cur];
       const double* oim = CPLX ? s_im[cur] : nullptr;
       double* nre = s_re[cur ^ 1];
       double* nim = CPLX ? s_im[cur ^ 1] : nullptr;
-      for (int t = tid; t < S; t += kBlock) {
+      for (int r = c0 + tid; r < c1; r += kBlock) {
+        const int M = s_cls[r];
+        const int Q = (M << 1) | b0;
         double vr = 0.0, vi = 0.0;
-#pragma unroll
-        for (int b0 = 0; b0 < 2; ++b0) {
-          const int Q = (t << 1) | b0;
-          if ((Q >> TOP) & 1) {
-            const int o = Q ^ (1 << TOP);
-            const double xr = ore[o];
-            vr = fma(xr, ar[TOP], vr);
+        if ((Q >> TOP) & 1) {
+          const int o = Q ^ (1 << TOP);
+          const double xr = ore[o];
+          vr = xr * s_ar[TOP];
+          if constexpr (CPLX) {
+            const double xi = oim[o];
+            vr = fma(-xi, s_ai[TOP], vr);
+            vi = fma(xr, s_ai[TOP], xi * s_ar[TOP]);
+          }
+        } else {
+          for (int q = Q & ~1; q; q &= q - 1) {
+            const int c = __ffs(q) - 1;
+            const int o = Q ^ (1 << c);
+            const double xr = ore[o], ar = s_ar[c];
+            vr = fma(xr, ar, vr);
             if constexpr (CPLX) {
-              const double xi = oim[o];
-              vr = fma(-xi, ai[TOP], vr);
-              vi = fma(xr, ai[TOP], fma(xi, ar[TOP], vi));
-            }
-          } else {
-#pragma unroll
-            for (int c = 1; c < TOP; ++c) {
-              if ((Q >> c) & 1) {
-                const int o = Q ^ (1 << c);
-                const double xr = ore[o];
-                vr = fma(xr, ar[c], vr);
-                if constexpr (CPLX) {
-                  const double xi = oim[o];
-                  vr = fma(-xi, ai[c], vr);
-                  vi = fma(xr, ai[c], fma(xi, ar[c], vi));
-                }
-              }
+              const double xi = oim[o], ai = s_ai[c];
+              vr = fma(-xi, ai, vr);
+              vi = fma(xr, ai, fma(xi, ar, vi));
             }
           }
         }
-        nre[t] = vr;
-        if constexpr (CPLX) nim[t] = vi;
+        nre[M] = vr;
+        if constexpr (CPLX) nim[M] = vi;
       }
       cur ^= 1;
       __syncthreads();
-      if ((i & 3) == 3 || i == n - 1) {  // renormalise by a power of two
+      if ((i & 3) == 3 || i == n - 1) {  // renormalise the class by a power of two
         double lm = 0.0;
-        for (int t = tid; t < S; t += kBlock) {
-          lm = fmax(lm, fabs(s_re[cur][t]));
-          if constexpr (CPLX) lm = fmax(lm, fabs(s_im[cur][t]));
+        for (int r = c0 + tid; r < c1; r += kBlock) {
+          const int M = s_cls[r];
+          lm = fmax(lm, fabs(s_re[cur][M]));
+          if constexpr (CPLX) lm = fmax(lm, fabs(s_im[cur][M]));
         }
         lm = wave_max(lm);
         if ((tid & (kWave - 1)) == 0) s_mx[tid / kWave] = lm;
         __syncthreads();
-        double M = s_mx[0];
+        double Mx = s_mx[0];
 #pragma unroll
-        for (int w = 1; w < kWavesPerBlock; ++w) M = fmax(M, s_mx[w]);
+        for (int w = 1; w < kWavesPerBlock; ++w) Mx = fmax(Mx, s_mx[w]);
         int ex = 0;
-        if (M > 0.0 && isfinite(M)) frexp(M, &ex);
+        if (Mx > 0.0 && isfinite(Mx)) frexp(Mx, &ex);
         if (ex != 0) {
-          for (int t = tid; t < S; t += kBlock) {
-            s_re[cur][t] = ldexp(s_re[cur][t], -ex);
-            if constexpr (CPLX) s_im[cur][t] = ldexp(s_im[cur][t], -ex);
+          for (int r = c0 + tid; r < c1; r += kBlock) {
+            const int M = s_cls[r];
+            s_re[cur][M] = ldexp(s_re[cur][M], -ex);
+            if constexpr (CPLX) s_im[cur][M] = ldexp(s_im[cur][M], -ex);
           }
         }
         esum += ex;
         __syncthreads();
       }
     }
-    // set every remaining x_j = 1: the sum of the coefficients, fixed order
+    // set every remaining x_j = 1: the sum of the class's coefficients, fixed order
+    const int pl = n < K + 1 ? n : K + 1;
     dd r{0.0, 0.0}, q{0.0, 0.0};
-    for (int t = tid; t < S; t += kBlock) {
-      dd_acc(r, s_re[cur][t]);
-      if constexpr (CPLX) dd_acc(q, s_im[cur][t]);
+    for (int t = s_cls_start[pl] + tid; t < s_cls_start[pl + 1]; t += kBlock) {
+      dd_acc(r, s_re[cur][s_cls[t]]);
+      if constexpr (CPLX) dd_acc(q, s_im[cur][s_cls[t]]);
     }
     s_red[tid] = r;
     if constexpr (CPLX) s_red_i[tid] = q;
