@@ -157,8 +157,9 @@ __device__ __forceinline__ u128 walk_chunk_pairs(const double* __restrict__ stag
   return fold(B);
 }
 
-// VARIANT 0: plain walk; VARIANT 1: pair-shared walk.  status[1] (set by the
-// staging kernel) says which one the matrix allows; the other exits at once.
+// VARIANT 0: plain walk; VARIANT 1: the pair-shared walk when status[1] (set
+// by the staging kernel) allows it, else the plain walk -- one launch, a
+// wave-uniform branch.
 template <int N, bool DRIFT, bool SINGLE, int VARIANT>
 __global__ __launch_bounds__(kBlock) void walk_int01_kernel(WalkArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -166,18 +167,23 @@ __global__ __launch_bounds__(kBlock) void walk_int01_kernel(WalkArgs a) {
   const uint64_t nwaves = (uint64_t)gridDim.x * kWavesPerBlock;
   u128 acc{0, 0};
   double drift = 0.0;
-  if (a.status[0] == kStOk && a.status[1] == VARIANT) {
+  if (a.status[0] == kStOk) {
+    const bool pairs = VARIANT == 1 && a.status[1] == 1;
     for (uint64_t task = wave; task < a.ntasks; task += nwaves) {
       const uint64_t c = task_chunk(task, lane);
       const uint32_t gpar = (uint32_t)((a.first + (task & 1)) & 1);
       double dr = 0.0;
       u128 part;
-      if constexpr (SINGLE)
+      if constexpr (SINGLE) {
         part = single_term<N>(a.staged, a.first + c);
-      else if constexpr (VARIANT == 1)
-        part = walk_chunk_pairs<N>(a.staged, a.first + c, a.b, gpar);
-      else
+      } else if constexpr (VARIANT == 1) {
+        if (pairs)
+          part = walk_chunk_pairs<N>(a.staged, a.first + c, a.b, gpar);
+        else
+          part = walk_chunk<N, DRIFT>(a.staged, a.first + c, a.b, gpar, dr);
+      } else {
         part = walk_chunk<N, DRIFT>(a.staged, a.first + c, a.b, gpar, dr);
+      }
       if (c < a.nchunks) {
         acc = u128_add(acc, part);
         drift = fmax(drift, dr);

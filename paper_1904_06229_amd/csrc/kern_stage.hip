@@ -131,30 +131,41 @@ __global__ __launch_bounds__(kBlock) void stage_int01_kernel(const uint8_t* __re
     for (int i = 0; i < n; ++i) c += s_a[i * kMaxN + j];
     s_csum[j] = c;
   }
+  __shared__ int32_t s_best;
+  __syncthreads();
+  const bool permute = pair_rows > 0 && !s_bad;
+  // the sparsest column (lowest index among equals): one wave's min-reduction
+  if (permute && tid < kWave) {
+    int key = tid < n ? (s_csum[tid] << 8) | tid : 0x7fffffff;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) key = min(key, __shfl_xor(key, off));
+    if (tid == 0) s_best = key & 0xff;
+  }
+  __syncthreads();
+  if (permute && tid < n) {
+    const int best = s_best;
+    // columns: the sparsest first, the others in their order
+    s_col[tid == 0 ? 0 : tid] = tid == 0 ? best : (tid <= best ? tid - 1 : tid);
+    // rows: those with a one in the sparsest column first (in index order), then
+    // the others by ascending degree (index order among equals); each row's
+    // place is the number of rows that precede it
+    const int i = tid;
+    const bool top = s_a[i * kMaxN + best] != 0;
+    int rank = 0;
+    for (int q = 0; q < n; ++q) {
+      const bool qtop = s_a[q * kMaxN + best] != 0;
+      if (top)
+        rank += (qtop && q < i) ? 1 : 0;
+      else
+        rank += (qtop || s_deg[q] < s_deg[i] || (s_deg[q] == s_deg[i] && q < i)) ? 1 : 0;
+    }
+    s_row[rank] = i;
+  }
   __syncthreads();
   if (tid == 0) {
     int pairs_ok = 0, ones0 = 0;
-    if (pair_rows > 0 && !s_bad) {
-      int best = 0;
-      for (int j = 1; j < n; ++j)
-        if (s_csum[j] < s_csum[best]) best = j;
-      ones0 = s_csum[best];
-      s_col[0] = best;
-      for (int j = 0, q = 1; j < n; ++j)
-        if (j != best) s_col[q++] = j;
-      int q = 0;
-      for (int i = 0; i < n; ++i)
-        if (s_a[i * kMaxN + best]) s_row[q++] = i;
-      const int top = q;
-      for (int i = 0; i < n; ++i)
-        if (!s_a[i * kMaxN + best]) {  // insertion by ascending degree (stable)
-          int p = q++;
-          while (p > top && s_deg[s_row[p - 1]] > s_deg[i]) {
-            s_row[p] = s_row[p - 1];
-            --p;
-          }
-          s_row[p] = i;
-        }
+    if (permute) {
+      ones0 = s_csum[s_best];
       if (ones0 <= pair_rows) {
         double prod = 1.0;  // exact while below 2^53; only compared with 2^50
         for (int i = 0; i < pair_rows && i < n; ++i) prod *= (double)s_deg[s_row[i]];

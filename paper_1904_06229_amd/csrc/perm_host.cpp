@@ -4,8 +4,8 @@
 // Launch sequence of a single-matrix call (all on the caller's stream):
 //   stage (validate, row exponents, +A/-A)  ->  walk: head (single terms),
 //   body (aligned chunks), tail (single terms)  ->  finish (fixed-order sum of
-//   the per-workgroup partials)  ->  copy of one small record to pinned host
-//   memory  ->  wait for the stream  ->  scale by 2(-1)^n and 2^-(row exponents).
+//   the per-workgroup partials, written straight into a pinned host record)
+//   ->  wait for the stream  ->  scale by 2(-1)^n and 2^-(row exponents).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,7 +45,8 @@ constexpr int kInt01ChunkCap = 10;
 struct Workspace {
   int device = -1;
   char* dmem = nullptr;
-  DevResult* hres = nullptr;
+  DevResult* hres = nullptr;      // pinned host record
+  DevResult* hres_dev = nullptr;  // the same record as the device addresses it
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   int cu_count = 0;
   // device sub-buffers
@@ -102,6 +103,15 @@ perm_status get_workspace(Workspace** out) {
     (void)hipFree(w->dmem);
     delete w;
     return fail(PERM_ENOMEM, std::string("hipHostMalloc failed: ") + hipGetErrorString(e));
+  }
+  // The finishing kernel writes the result record straight into pinned host
+  // memory (no separate copy); the stream synchronisation makes it visible.
+  e = hipHostGetDevicePointer((void**)&w->hres_dev, w->hres, 0);
+  if (e != hipSuccess) {
+    (void)hipHostFree(w->hres);
+    (void)hipFree(w->dmem);
+    delete w;
+    return fail(PERM_EHIP, std::string("hipHostGetDevicePointer failed: ") + hipGetErrorString(e));
   }
   for (auto& ev : w->ev) {
     e = hipEventCreate(&ev);
@@ -243,19 +253,15 @@ perm_status run_range(int kind, const void* dA, int n, int ld, uint64_t start, u
 
   HIP_TRY(hipEventRecord(ws->ev[1], s));
   if ((st = walk(plan.head_start, plan.head_count, 0, 0, nullptr)) != PERM_OK) return st;
-  if ((st = walk(plan.body_first_chunk, plan.body_chunks, plan.log2_chunk, 0, &body_grid)) !=
-      PERM_OK)
-    return st;
-  // Pair-shared 0/1 walk: launched next to the plain one; the staging kernel's
-  // flag makes exactly one of the two do the work.
-  if (pair_rows > 0 &&
-      (st = walk(plan.body_first_chunk, plan.body_chunks, plan.log2_chunk, 1, nullptr)) != PERM_OK)
+  // Pair-shared 0/1 walk: the walk kernel takes it when the staging kernel's
+  // flag allows it, else walks plainly (one launch).
+  if ((st = walk(plan.body_first_chunk, plan.body_chunks, plan.log2_chunk, pair_rows > 0 ? 1 : 0,
+                 &body_grid)) != PERM_OK)
     return st;
   if ((st = walk(plan.tail_start, plan.tail_count, 0, 0, nullptr)) != PERM_OK) return st;
   HIP_TRY(hipEventRecord(ws->ev[2], s));
   HIP_TRY(launch_finish(kind, ws->partials, nparts, ws->drift, drift ? 1 : 0, ws->status,
-                        ws->rowexp, n, ws->bound, ws->dres, s));
-  HIP_TRY(hipMemcpyAsync(ws->hres, ws->dres, sizeof(DevResult), hipMemcpyDeviceToHost, s));
+                        ws->rowexp, n, ws->bound, ws->hres_dev, s));
   HIP_TRY(hipEventRecord(ws->ev[3], s));
   HIP_TRY(hipStreamSynchronize(s));
   raw->r = *ws->hres;

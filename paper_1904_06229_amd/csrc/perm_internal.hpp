@@ -64,9 +64,9 @@ hipError_t launch_walk_int01_lo(int n, bool drift, int variant, const WalkArgs& 
                                 hipStream_t s);
 hipError_t launch_walk_int01_hi(int n, bool drift, int variant, const WalkArgs& a, int grid,
                                 hipStream_t s);
-// 0/1 walk variant 0: plain exact walk; 1: pair-shared walk (the staging
-// kernel's status[1] decides at run time which of the two launched variants
-// works).
+// 0/1 walk variant 0: plain exact walk; 1: the pair-shared walk where the
+// staging kernel's status[1] allows it, the plain walk otherwise (decided on
+// the device, in one launch).
 // Smallest pair_rows (n/3) for which the pair-shared 0/1 walk is built.
 constexpr int kInt01PairMinRows = 3;
 
