@@ -99,6 +99,8 @@ def parse():
                    choices=["c1", "c2", "c3", "c4", "c5", "c6", "c7", "c8"])
     p.add_argument("--count", type=int, default=100000, help="c4: number of matrices")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-autotune", action="store_true",
+                   help="c4: use the default chunk lengths instead of tuning them first")
     p.add_argument("--blocks", type=int, default=0)
     p.add_argument("--log2-chunk", type=int, default=0)
     p.add_argument("--precision", default="dd")
@@ -199,7 +201,8 @@ def bench_batched(args):
     out = torch.zeros(4 * count, dtype=torch.float64, device="cuda")
     st = torch.zeros(count, dtype=torch.int32, device="cuda")
     t1 = time.perf_counter()
-    B.perm_autotune(True, 8, 24)
+    if not args.no_autotune:
+        B.perm_autotune(True, 8, 24)
     tune_s = time.perf_counter() - t1
     s = torch.cuda.Stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -22,7 +22,7 @@
  *     enqueued on it.  Single-matrix calls wait for that stream and return a
  *     host value; perm_batched only enqueues and returns at once.
  *   - No pointer is kept after a call returns.  Library-owned device
- *     workspace (staged matrix, partial sums, queue) is allocated lazily per
+ *     workspace (staged matrix, partial sums, item plans) is allocated lazily per
  *     device and kept until perm_release().  Calls that overlap on one device
  *     (several host threads, or several streams) are not supported.
  *   - Errors are reported only through the returned status; on error the
@@ -149,9 +149,8 @@ perm_status perm_partial(int dtype, const void* dA, int n, int ld, uint64_t star
                          void* stream);
 
 /*
- * perm_batched -- permanents of many independent matrices in one persistent
- * launch (the random-matrix studies of Secs. III-VI compute many
- * independent permanents).
+ * perm_batched -- permanents of many independent matrices (the random-matrix
+ * studies of Secs. III-VI compute many independent permanents).
  *   dA       device array holding the matrices back to back; matrix m starts at
  *            element offset h_offset[m] (in doubles) and is column-major with
  *            ld = n_m (complex: interleaved pairs, offset still in doubles).
@@ -162,8 +161,9 @@ perm_status perm_partial(int dtype, const void* dA, int n, int ld, uint64_t star
  *   d_status device array of count int32 (may be NULL): PERM_OK or PERM_ENONFINITE.
  * Work is bucketed by n (largest first), cut into wave-sized items of
  * 2^log2_chunk-term lane chunks (per-n lengths from the autotuner unless
- * opts->log2_chunk is set), and pulled from a device queue by a persistent
- * kernel.  Enqueued on `stream`; returns without waiting.
+ * opts->log2_chunk is set); each size runs as one persistent launch of that
+ * size's kernel, the waves taking its items round-robin (items of one size cost
+ * the same).  Enqueued on `stream`; returns without waiting.
  */
 perm_status perm_batched(const double* dA, const int32_t* h_n, const int64_t* h_offset,
                          int count, int is_complex, const perm_opts* opts, double* d_out,

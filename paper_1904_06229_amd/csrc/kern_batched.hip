@@ -2,13 +2,12 @@
 // of Secs. III-VI evaluate many independent permanents).
 //
 //   stage    one workgroup per matrix: validate, row exponents, +A/-A copy
-//   reset    queue head <- 0 (a kernel, so the sequence can be captured in a
-//            HIP graph without memset nodes)
-//   walk     persistent kernel: each wave takes the next item from the queue
-//            (an atomic counter on the item array, which the host sorted by
-//            size, largest first), walks its 64 lane chunks with the same
-//            chunk walk as the single-matrix kernels, and writes the wave's
-//            sum into the item's slot
+//   walk     one persistent launch per matrix size (largest first): the
+//            items of one size are contiguous in the item array and cost the
+//            same, so wave w takes items w, w + W, w + 2W, ... (W waves in the
+//            grid) with no queue; each item's 64 lane chunks are walked with
+//            the same chunk walk as the single-matrix kernels, fully inlined
+//            for that size, and the wave's sum goes into the item's slot
 //   finish   one thread per matrix adds its items' slots in item order
 //            (fixed order, so results are reproducible) and scales by
 //            2(-1)^n and the row-scaling factor
@@ -77,99 +76,60 @@ __global__ __launch_bounds__(kBlock) void batched_stage_kernel(
   }
 }
 
-__global__ void batched_reset_kernel(unsigned int* counter) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0u;
-}
-
 typedef const __attribute__((address_space(4))) BatchItem* citem_ptr;
 typedef const __attribute__((address_space(4))) int64_t* ci64_ptr;
 typedef const __attribute__((address_space(4))) int32_t* ci32_ptr;
 
-__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-  return ((uint64_t)hi << 32) | lo;
-}
-
-// One queue item.  Not inlined: each size gets its own register allocation
-// (inlined into one switch, the sizes' code is merged and the kernel needs
-// the registers of the largest size plus more).  Arguments of a call arrive
-// in VGPRs, so the uniform ones are moved back to SGPRs first.
+// The items [item0, item0 + nitems), all of size N.
 template <int N, int MODE, bool CPLX>
-__device__ __attribute__((noinline)) void run_item(const double* st_arg, uint64_t task_arg,
-                                                   int b_arg, uint64_t nchunks_arg,
-                                                   double* slot_arg) {
-  const double* st = (const double*)uniform64((uint64_t)st_arg);
-  const uint64_t task = uniform64(task_arg);
-  const int b = __builtin_amdgcn_readfirstlane(b_arg);
-  const uint64_t nchunks = uniform64(nchunks_arg);
+__global__ __launch_bounds__(kBlock) void batched_size_kernel(BatchArgs a, uint64_t item0,
+                                                              uint64_t nitems) {
   const int lane = threadIdx.x & (kWave - 1);
-  const uint64_t c = task_chunk(task, lane);
-  const uint32_t gpar = (uint32_t)(task & 1);
-  double dr = 0.0;
-  dd re{0.0, 0.0}, im{0.0, 0.0};
-  // n = 1 has a single term; every larger size is planned with b >= 1.
-  if constexpr (CPLX) {
-    const cdd p = (N == 1) ? single_term_complex<N, MODE>(st, c)
-                           : walk_chunk_complex<N, MODE, false>(st, nullptr, c, b, gpar, dr);
-    re = p.re;
-    im = p.im;
-  } else {
-    re = (N == 1) ? single_term_real<N, MODE>(st, c)
-                  : walk_chunk_real<N, MODE, false>(st, nullptr, c, b, gpar, dr);
-  }
-  if (c >= nchunks) {
-    re = dd{0.0, 0.0};
-    im = dd{0.0, 0.0};
-  }
-  re = wave_sum(re);
-  if constexpr (CPLX) im = wave_sum(im);
-  if (lane == 0) {
-    slot_arg[0] = re.hi;
-    slot_arg[1] = re.lo;
-    slot_arg[2] = im.hi;
-    slot_arg[3] = im.lo;
-  }
-}
-
-#define PERM_BCASE(N)                                   \
-  case N:                                               \
-    if constexpr (N <= MAXN) run_item<N, MODE, CPLX>(st, it.task, it.b, it.nchunks, slot); \
-    break;
-
-template <int MAXN, int MODE, bool CPLX>
-__global__ __launch_bounds__(kBlock) void batched_walk_kernel(BatchArgs a) {
-  const int lane = threadIdx.x & (kWave - 1);
-  for (;;) {
-    unsigned int got = 0;
-    if (lane == 0) got = atomicAdd(a.counter, 1u);
-    const uint64_t idx = (uint64_t)__builtin_amdgcn_readfirstlane(__shfl(got, 0));
-    if (idx >= a.nitems) break;  // every wave reaches this once the queue is drained
+  const uint64_t wave = wave_id();
+  const uint64_t nwaves = (uint64_t)gridDim.x * kWavesPerBlock;
+  for (uint64_t q = wave; q < nitems; q += nwaves) {
+    const uint64_t idx = item0 + q;
     const citem_ptr ip = (citem_ptr)a.items + idx;
-    BatchItem it;
-    it.mat = ip->mat;
-    it.n = ip->n;
-    it.b = ip->b;
-    it.task = ip->task;
-    it.nchunks = ip->nchunks;
-    if (((ci32_ptr)a.mstatus)[it.mat] != kStOk) {
-      if (lane == 0) {
-        double* s = a.slots + 4 * idx;
-        s[0] = s[1] = s[2] = s[3] = 0.0;
-      }
+    const int mat = ip->mat;
+    const int b = ip->b;
+    const uint64_t task = ip->task;
+    const uint64_t nchunks = ip->nchunks;
+    double* slot = a.slots + 4 * idx;
+    if (((ci32_ptr)a.mstatus)[mat] != kStOk) {
+      if (lane == 0) slot[0] = slot[1] = slot[2] = slot[3] = 0.0;
       continue;
     }
-    const double* st = a.staged + ((ci64_ptr)a.st_off)[it.mat];
-    double* slot = a.slots + 4 * idx;
-    switch (it.n) {
-      PERM_BCASE(1) PERM_BCASE(2) PERM_BCASE(3) PERM_BCASE(4) PERM_BCASE(5) PERM_BCASE(6)
-      PERM_BCASE(7) PERM_BCASE(8) PERM_BCASE(9) PERM_BCASE(10) PERM_BCASE(11) PERM_BCASE(12)
-      PERM_BCASE(13) PERM_BCASE(14) PERM_BCASE(15) PERM_BCASE(16) PERM_BCASE(17)
-      PERM_BCASE(18) PERM_BCASE(19) PERM_BCASE(20) PERM_BCASE(21) PERM_BCASE(22)
-      PERM_BCASE(23) PERM_BCASE(24) PERM_BCASE(25) PERM_BCASE(26) PERM_BCASE(27)
-      PERM_BCASE(28) PERM_BCASE(29) PERM_BCASE(30) PERM_BCASE(31) PERM_BCASE(32)
-      default:
-        break;
+    const double* st = a.staged + ((ci64_ptr)a.st_off)[mat];
+    const uint64_t c = task_chunk(task, lane);
+    const uint32_t gpar = (uint32_t)(task & 1);
+    double dr = 0.0;
+    dd re{0.0, 0.0}, im{0.0, 0.0};
+    // n = 1 has a single term; every larger size is planned with b >= 1.
+    if constexpr (CPLX) {
+      cdd p;
+      if constexpr (N == 1)
+        p = single_term_complex<N, MODE>(st, c);
+      else
+        p = walk_chunk_complex<N, MODE, false>(st, nullptr, c, b, gpar, dr);
+      re = p.re;
+      im = p.im;
+    } else {
+      if constexpr (N == 1)
+        re = single_term_real<N, MODE>(st, c);
+      else
+        re = walk_chunk_real<N, MODE, false>(st, nullptr, c, b, gpar, dr);
+    }
+    if (c >= nchunks) {
+      re = dd{0.0, 0.0};
+      im = dd{0.0, 0.0};
+    }
+    re = wave_sum(re);
+    if constexpr (CPLX) im = wave_sum(im);
+    if (lane == 0) {
+      slot[0] = re.hi;
+      slot[1] = re.lo;
+      slot[2] = im.hi;
+      slot[3] = im.lo;
     }
   }
 }
@@ -205,36 +165,51 @@ __global__ __launch_bounds__(kBlock) void batched_finish_kernel(
   if (status_out) status_out[m] = st;
 }
 
+template <int N, int MODE, bool CPLX>
+const void* size_kernel() {
+  return (const void*)batched_size_kernel<N, MODE, CPLX>;
+}
+
 template <int MODE, bool CPLX>
-hipError_t launch_walk_maxn(int max_n, const BatchArgs& a, int grid, hipStream_t s) {
-  const dim3 g(grid), b(kBlock);
-  if (max_n <= 16)
-    hipLaunchKernelGGL((batched_walk_kernel<16, MODE, CPLX>), g, b, 0, s, a);
-  else if (max_n <= 24)
-    hipLaunchKernelGGL((batched_walk_kernel<24, MODE, CPLX>), g, b, 0, s, a);
-  else
-    hipLaunchKernelGGL((batched_walk_kernel<32, MODE, CPLX>), g, b, 0, s, a);
-  return hipGetLastError();
+const void* size_kernel_by_n(int n) {
+  switch (n) {
+#define PERM_BK(N) \
+  case N:          \
+    return size_kernel<N, MODE, CPLX>();
+    PERM_BK(1) PERM_BK(2) PERM_BK(3) PERM_BK(4) PERM_BK(5) PERM_BK(6) PERM_BK(7) PERM_BK(8)
+    PERM_BK(9) PERM_BK(10) PERM_BK(11) PERM_BK(12) PERM_BK(13) PERM_BK(14) PERM_BK(15)
+    PERM_BK(16) PERM_BK(17) PERM_BK(18) PERM_BK(19) PERM_BK(20) PERM_BK(21) PERM_BK(22)
+    PERM_BK(23) PERM_BK(24) PERM_BK(25) PERM_BK(26) PERM_BK(27) PERM_BK(28) PERM_BK(29)
+    PERM_BK(30) PERM_BK(31) PERM_BK(32)
+#undef PERM_BK
+    default:
+      return nullptr;
+  }
+}
+
+const void* size_kernel_ptr(int is_complex, int mode, int n) {
+  if (mode == 0) return is_complex ? size_kernel_by_n<0, true>(n) : size_kernel_by_n<0, false>(n);
+  if (mode == 1) return is_complex ? size_kernel_by_n<1, true>(n) : size_kernel_by_n<1, false>(n);
+  return nullptr;
 }
 
 }  // namespace
 
-int batched_walk_blocks_per_cu(int is_complex, int mode, int max_n) {
-  const void* f = nullptr;
-#define PERM_PICK(MODE, C)                                                        \
-  f = max_n <= 16 ? (const void*)batched_walk_kernel<16, MODE, C>                 \
-                  : (max_n <= 24 ? (const void*)batched_walk_kernel<24, MODE, C>  \
-                                 : (const void*)batched_walk_kernel<32, MODE, C>);
-  if (mode == 0) {
-    if (is_complex) { PERM_PICK(0, true) } else { PERM_PICK(0, false) }
-  } else {
-    if (is_complex) { PERM_PICK(1, true) } else { PERM_PICK(1, false) }
-  }
-#undef PERM_PICK
+int batched_walk_blocks_per_cu(int is_complex, int mode, int n) {
+  const void* f = size_kernel_ptr(is_complex, mode, n);
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kBlock, 0) != hipSuccess || nb < 1)
+  if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kBlock, 0) != hipSuccess || nb < 1)
     nb = 1;
   return nb;
+}
+
+hipError_t launch_batched_size(int is_complex, int mode, int n, const BatchArgs& a,
+                               uint64_t item0, uint64_t nitems, int grid, hipStream_t s) {
+  const void* f = size_kernel_ptr(is_complex, mode, n);
+  if (!f) return hipErrorInvalidValue;
+  BatchArgs args = a;
+  void* params[] = {&args, &item0, &nitems};
+  return hipLaunchKernel(f, dim3(grid), dim3(kBlock), params, 0, s);
 }
 
 hipError_t launch_batched_stage(int is_complex, const double* A, const int64_t* d_off,
@@ -245,22 +220,6 @@ hipError_t launch_batched_stage(int is_complex, const double* A, const int64_t* 
   hipLaunchKernelGGL(batched_stage_kernel, dim3(count), dim3(kBlock), 0, s, A, d_off, d_n,
                      is_complex, row_scaling, staged, st_off, rowexp_sum, mstatus);
   return hipGetLastError();
-}
-
-hipError_t launch_batched_reset(unsigned int* counter, hipStream_t s) {
-  hipLaunchKernelGGL(batched_reset_kernel, dim3(1), dim3(64), 0, s, counter);
-  return hipGetLastError();
-}
-
-hipError_t launch_batched_walk(int is_complex, int mode, int max_n, const BatchArgs& a, int grid,
-                               hipStream_t s) {
-  if (mode == 0)
-    return is_complex ? launch_walk_maxn<0, true>(max_n, a, grid, s)
-                      : launch_walk_maxn<0, false>(max_n, a, grid, s);
-  if (mode == 1)
-    return is_complex ? launch_walk_maxn<1, true>(max_n, a, grid, s)
-                      : launch_walk_maxn<1, false>(max_n, a, grid, s);
-  return hipErrorInvalidValue;
 }
 
 hipError_t launch_batched_finish(const double* slots, const int64_t* item_first,

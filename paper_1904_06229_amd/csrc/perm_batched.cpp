@@ -1,11 +1,13 @@
 // Host side of the batched path: queue construction, per-device plan cache,
 // HIP graph capture and replay, and the chunk-length autotuner.
 //
-// The queue: matrices are sorted by size, largest first (the largest pieces of
-// work start first, so the persistent kernel's tail is made of small items),
-// and each matrix of size n contributes 2*ceil(C/128) wave items, C = 2^(n-1-b)
-// lane chunks of 2^b terms.  b comes from the autotuned table for n, or from
+// The items: matrices are sorted by size, largest first, and each matrix of
+// size n contributes 2*ceil(C/128) wave items, C = 2^(n-1-b) lane chunks of
+// 2^b terms.  b comes from the autotuned table for n, or from
 // opts->log2_chunk, or from a default that gives items of about 2^16 terms.
+// The items of one size are contiguous and cost the same: each size runs as
+// one persistent launch of that size's kernel (its own register allocation),
+// the waves taking the items round-robin.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -59,10 +61,13 @@ struct Plan {
   int64_t* item_first = nullptr;
   int32_t* item_count = nullptr;
   double* slots = nullptr;
-  unsigned int* counter = nullptr;
   uint64_t nitems = 0;
-  int max_n = 0;
-  int grid = 0;
+  struct Group {
+    int n;
+    uint64_t item0, nitems;
+    int grid;
+  };
+  std::vector<Group> groups;  // by size, largest first
   hipGraphExec_t gexec = nullptr;
   hipStream_t gstream = nullptr;
 };
@@ -125,10 +130,11 @@ perm_status build_plan(Plan* p, int dev) {
   std::vector<BatchItem> items;
   std::vector<int64_t> item_first(count);
   std::vector<int32_t> item_count(count);
-  p->max_n = 0;
+  p->groups.clear();
   for (int m : order) {
     const int n = p->n[m];
-    p->max_n = std::max(p->max_n, n);
+    if (p->groups.empty() || p->groups.back().n != n)
+      p->groups.push_back(Plan::Group{n, (uint64_t)items.size(), 0, 0});
     const int b = pick_b(p->is_complex, n, p->lc);
     const uint64_t C = 1ull << (n - 1 - b);
     const uint64_t tasks = 2 * ((C + 2 * kWave - 1) / (2 * kWave));
@@ -144,6 +150,7 @@ perm_status build_plan(Plan* p, int dev) {
       it.nchunks = C;
       items.push_back(it);
     }
+    p->groups.back().nitems += tasks;
   }
   p->nitems = items.size();
   size_t off = 0;
@@ -162,7 +169,6 @@ perm_status build_plan(Plan* p, int dev) {
   const size_t o_if = take(sizeof(int64_t) * count);
   const size_t o_ic = take(sizeof(int32_t) * count);
   const size_t o_slots = take(sizeof(double) * 4 * items.size());
-  const size_t o_ctr = take(sizeof(unsigned int) * 64);
   hipError_t e = hipMalloc((void**)&p->mem, off);
   if (e != hipSuccess) {
     p->mem = nullptr;
@@ -178,7 +184,6 @@ perm_status build_plan(Plan* p, int dev) {
   p->item_first = (int64_t*)(p->mem + o_if);
   p->item_count = (int32_t*)(p->mem + o_ic);
   p->slots = (double*)(p->mem + o_slots);
-  p->counter = (unsigned int*)(p->mem + o_ctr);
   struct Up {
     void* dst;
     const void* src;
@@ -196,11 +201,13 @@ perm_status build_plan(Plan* p, int dev) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
     cus = prop.multiProcessorCount;
-  const int nb = batched_walk_blocks_per_cu(p->is_complex, p->mode, p->max_n);
-  uint64_t grid = (uint64_t)cus * nb;
-  const uint64_t need = (p->nitems + kWavesPerBlock - 1) / kWavesPerBlock;
-  if (grid > need) grid = need;
-  p->grid = (int)std::max<uint64_t>(grid, 1);
+  for (Plan::Group& g : p->groups) {
+    const int nb = batched_walk_blocks_per_cu(p->is_complex, p->mode, g.n);
+    uint64_t grid = (uint64_t)cus * nb;
+    const uint64_t need = (g.nitems + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (grid > need) grid = need;
+    g.grid = (int)std::max<uint64_t>(grid, 1);
+  }
   return PERM_OK;
 }
 
@@ -210,14 +217,13 @@ perm_status enqueue(Plan* p, hipStream_t s) {
   a.st_off = p->st_off;
   a.mstatus = p->mstatus;
   a.items = p->items;
-  a.nitems = p->nitems;
-  a.counter = p->counter;
   a.slots = p->slots;
   hipError_t e = launch_batched_stage(p->is_complex, p->dA, p->d_off, p->d_n, p->count,
                                       p->row_scaling, p->staged, p->st_off, p->exp_sum,
                                       p->mstatus, s);
-  if (e == hipSuccess) e = launch_batched_reset(p->counter, s);
-  if (e == hipSuccess) e = launch_batched_walk(p->is_complex, p->mode, p->max_n, a, p->grid, s);
+  for (const Plan::Group& g : p->groups)
+    if (e == hipSuccess)
+      e = launch_batched_size(p->is_complex, p->mode, g.n, a, g.item0, g.nitems, g.grid, s);
   if (e == hipSuccess)
     e = launch_batched_finish(p->slots, p->item_first, p->item_count, p->d_n, p->exp_sum,
                               p->mstatus, p->count, p->d_out, p->d_status, s);

@@ -99,9 +99,7 @@ struct BatchArgs {
   const double* staged;      // staged matrices (per matrix: +A then -A)
   const int64_t* st_off;     // offset of matrix m's staged block (doubles)
   const int32_t* mstatus;    // per-matrix staging status
-  const BatchItem* items;
-  uint64_t nitems;
-  unsigned int* counter;     // queue head; reset to 0 before every launch
+  const BatchItem* items;    // sorted by size, largest first
   double* slots;             // 4 doubles per item
 };
 
@@ -109,15 +107,15 @@ hipError_t launch_batched_stage(int is_complex, const double* A, const int64_t* 
                                 const int32_t* d_n, int count, int row_scaling, double* staged,
                                 const int64_t* st_off, int32_t* rowexp_sum, int32_t* mstatus,
                                 hipStream_t s);
-hipError_t launch_batched_walk(int is_complex, int mode, int max_n, const BatchArgs& a, int grid,
-                               hipStream_t s);
-hipError_t launch_batched_reset(unsigned int* counter, hipStream_t s);
+// Items [item0, item0 + nitems), all of size n, by the size's own kernel.
+hipError_t launch_batched_size(int is_complex, int mode, int n, const BatchArgs& a,
+                               uint64_t item0, uint64_t nitems, int grid, hipStream_t s);
 hipError_t launch_batched_finish(const double* slots, const int64_t* item_first,
                                  const int32_t* item_count, const int32_t* d_n,
                                  const int32_t* rowexp_sum, const int32_t* mstatus, int count,
                                  double* d_out, int32_t* d_status, hipStream_t s);
-// Resident workgroups per CU of the persistent kernel for this configuration.
-int batched_walk_blocks_per_cu(int is_complex, int mode, int max_n);
+// Resident workgroups per CU of size n's batched kernel.
+int batched_walk_blocks_per_cu(int is_complex, int mode, int n);
 
 // ------------------------------------------------------ mixed-radix sums ----
 // Ryser-type sums whose column sets are enumerated digit by digit: repeated
