@@ -26,10 +26,13 @@
 // masks of one class (sorted by value, so a wave rarely mixes the two cases)
 // and walks their set bits; the row's band entries sit in LDS.
 //
-// One workgroup per matrix (grid-stride over the batch).  Powers of two keep
-// long products in range, exactly: each row's entries are scaled into
-// [1/2, 1), and every 4 rows the class's coefficients are scaled by the power
-// of two of their largest magnitude; the exponents are restored at the end.
+// One workgroup per matrix (grid-stride over the batch).  The next row's band
+// entries are loaded (as wave-uniform scalars) while the current row is
+// computed, and the rows' entries alternate between two LDS slots, so one
+// barrier per row suffices.  Powers of two keep long products in range,
+// exactly: each row's entries are scaled into [1/2, 1), and every 4 rows the
+// class's coefficients are scaled by the power of two of their largest
+// magnitude; the exponents are restored at the end.
 // The final coefficient sum is a fixed-order double-double tree.
 #include "perm_device.hpp"
 #include "perm_internal.hpp"
@@ -47,7 +50,7 @@ __global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
   __shared__ double s_im[CPLX ? 2 : 1][CPLX ? S : 1];
   __shared__ uint16_t s_cls[S];          // masks grouped by popcount, ascending in a group
   __shared__ int32_t s_cls_start[W + 2];
-  __shared__ double s_ar[W + 1], s_ai[CPLX ? W + 1 : 1];
+  __shared__ double s_ar[2][W + 1], s_ai[2][CPLX ? W + 1 : 1];
   __shared__ dd s_red[kBlock], s_red_i[CPLX ? kBlock : 1];
   __shared__ double s_mx[kWavesPerBlock];
   typedef const __attribute__((address_space(4))) int32_t* ci32;
@@ -72,31 +75,43 @@ __global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
     }
     int cur = 0, esum = 0;
     bool bad = false;
-    for (int i = 0; i < n; ++i) {
-      // band entries of row i: c = 1..2k+1 <-> column j = i-k-1+c (every
-      // thread reads them, as scalars, for the row's scale)
-      double mx = 0.0;
+    // Band entries of row i, c = 1..2k+1 <-> column j = i-k-1+c, as wave-uniform
+    // values; the next row's are loaded while the current row is computed.
+    double vr[TOP + 1], vi[TOP + 1];
+    auto load_row = [&](int i) {
 #pragma unroll
       for (int c = 1; c <= TOP; ++c) {
         const int j = i - K - 1 + c;
         const bool in = j >= 0 && j < n;
         cdptr p = as_const(A + (size_t)cw * ((size_t)i + (size_t)(in ? j : 0) * n));
-        const double vr = in ? p[0] : 0.0;
-        const double vi = (CPLX && in) ? p[1] : 0.0;
-        if (!isfinite(vr) || !isfinite(vi)) bad = true;
-        mx = fmax(mx, fmax(fabs(vr), fabs(vi)));
+        vr[c] = in ? p[0] : 0.0;
+        vi[c] = (CPLX && in) ? p[1] : 0.0;
+      }
+    };
+    load_row(0);
+    for (int i = 0; i < n; ++i) {
+      // row i's scale, and its entries into this row's LDS slot
+      double mx = 0.0;
+#pragma unroll
+      for (int c = 1; c <= TOP; ++c) {
+        if (!isfinite(vr[c]) || !isfinite(vi[c])) bad = true;
+        mx = fmax(mx, fmax(fabs(vr[c]), fabs(vi[c])));
       }
       int e = 0;
       if (mx > 0.0 && !bad) frexp(mx, &e);  // scale the row by 2^-e
       esum += e;
-      if (tid >= 1 && tid <= TOP) {
-        const int j = i - K - 1 + tid;
-        const bool in = j >= 0 && j < n;
-        const double* p = A + (size_t)cw * ((size_t)i + (size_t)(in ? j : 0) * n);
-        s_ar[tid] = in ? ldexp(p[0], -e) : 0.0;
-        if constexpr (CPLX) s_ai[tid] = in ? ldexp(p[1], -e) : 0.0;
-      }
+      const int ab = i & 1;
+#pragma unroll
+      for (int c = 1; c <= TOP; ++c)
+        if (tid == c) {
+          s_ar[ab][c] = ldexp(vr[c], -e);
+          if constexpr (CPLX) s_ai[ab][c] = ldexp(vi[c], -e);
+        }
+      if (i + 1 < n) load_row(i + 1);  // in flight during row i
+      // one barrier: row i's entries, and row i-1's coefficients, are in LDS
       __syncthreads();
+      const double* ar = s_ar[ab];
+      const double* ai = s_ai[CPLX ? ab : 0];
       const int pcls = i + 1 < K + 1 ? i + 1 : K + 1;
       const int b0 = (i - K - 1 >= 0) ? 1 : 0;
       const int c0 = s_cls_start[pcls], c1 = s_cls_start[pcls + 1];
@@ -107,35 +122,35 @@ __global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
       for (int r = c0 + tid; r < c1; r += kBlock) {
         const int M = s_cls[r];
         const int Q = (M << 1) | b0;
-        double vr = 0.0, vi = 0.0;
+        double xr_acc = 0.0, xi_acc = 0.0;
         if ((Q >> TOP) & 1) {
           const int o = Q ^ (1 << TOP);
           const double xr = ore[o];
-          vr = xr * s_ar[TOP];
+          xr_acc = xr * ar[TOP];
           if constexpr (CPLX) {
             const double xi = oim[o];
-            vr = fma(-xi, s_ai[TOP], vr);
-            vi = fma(xr, s_ai[TOP], xi * s_ar[TOP]);
+            xr_acc = fma(-xi, ai[TOP], xr_acc);
+            xi_acc = fma(xr, ai[TOP], xi * ar[TOP]);
           }
         } else {
           for (int q = Q & ~1; q; q &= q - 1) {
             const int c = __ffs(q) - 1;
             const int o = Q ^ (1 << c);
-            const double xr = ore[o], ar = s_ar[c];
-            vr = fma(xr, ar, vr);
+            const double xr = ore[o], arc = ar[c];
+            xr_acc = fma(xr, arc, xr_acc);
             if constexpr (CPLX) {
-              const double xi = oim[o], ai = s_ai[c];
-              vr = fma(-xi, ai, vr);
-              vi = fma(xr, ai, fma(xi, ar, vi));
+              const double xi = oim[o], aic = ai[c];
+              xr_acc = fma(-xi, aic, xr_acc);
+              xi_acc = fma(xr, aic, fma(xi, arc, xi_acc));
             }
           }
         }
-        nre[M] = vr;
-        if constexpr (CPLX) nim[M] = vi;
+        nre[M] = xr_acc;
+        if constexpr (CPLX) nim[M] = xi_acc;
       }
       cur ^= 1;
-      __syncthreads();
       if ((i & 3) == 3 || i == n - 1) {  // renormalise the class by a power of two
+        __syncthreads();
         double lm = 0.0;
         for (int r = c0 + tid; r < c1; r += kBlock) {
           const int M = s_cls[r];
@@ -158,9 +173,9 @@ __global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
           }
         }
         esum += ex;
-        __syncthreads();
       }
     }
+    __syncthreads();
     // set every remaining x_j = 1: the sum of the class's coefficients, fixed order
     const int pl = n < K + 1 ? n : K + 1;
     dd r{0.0, 0.0}, q{0.0, 0.0};
