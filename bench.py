@@ -365,18 +365,19 @@ def bench_band(args):
                     0) / math.sqrt(2.0)
     flat = np.ascontiguousarray(np.transpose(mats, (0, 2, 1))).ravel().view(np.float64)
     dA = torch.from_numpy(flat).to("cuda")
-    offs = [m * 2 * n * n for m in range(count)]
+    sizes = np.full(count, n, dtype=np.int32)
+    offs = np.arange(count, dtype=np.int64) * (2 * n * n)
     out = torch.zeros(4 * count, dtype=torch.float64, device="cuda")
     st = torch.zeros(count, dtype=torch.int32, device="cuda")
     for _ in range(args.warmup):
-        B.perm_band(dA, [n] * count, offs, k, True, out, st, blocks=args.blocks)
+        B.perm_band(dA, sizes, offs, k, True, out, st, blocks=args.blocks)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     kms = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ev0.record()
-        B.perm_band(dA, [n] * count, offs, k, True, out, st, blocks=args.blocks)
+        B.perm_band(dA, sizes, offs, k, True, out, st, blocks=args.blocks)
         ev1.record()
         ev1.synchronize()
         kms.append(ev0.elapsed_time(ev1))

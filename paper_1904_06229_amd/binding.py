@@ -329,13 +329,27 @@ def perm_sparse_partition(A, trials: int = 1, seed: int = 0, stream=None):
     return [int(x) for x in blk], nb.value, terms.value
 
 
+def _host_ints(seq, dtype):
+    """A C-contiguous host array of `dtype` holding `seq` (zero-copy for a
+    matching numpy array) and its address, for the size/offset arguments."""
+    import numpy as np
+    arr = np.ascontiguousarray(np.asarray(seq, dtype=dtype))
+    if arr.ndim != 1:
+        raise ValueError("sizes and offsets must be one-dimensional")
+    if arr.size == 0:
+        arr = np.zeros(1, dtype=dtype)
+    return arr, ctypes.c_void_p(arr.ctypes.data)
+
+
 def perm_band(A_packed, sizes, offsets, k: int, is_complex: bool, out, status=None, stream=None,
               **opts) -> None:
     """Band permanents (App. C) of the matrices packed in ``A_packed``; results in ``out``."""
     import torch
     count = len(sizes)
-    n_arr = (ctypes.c_int32 * max(count, 1))(*[int(x) for x in sizes])
-    o_arr = (ctypes.c_int64 * max(count, 1))(*[int(x) for x in offsets])
+    if len(offsets) != count:
+        raise ValueError("sizes and offsets differ in length")
+    n_keep, n_arr = _host_ints(sizes, "int32")
+    o_keep, o_arr = _host_ints(offsets, "int64")
     o = make_opts(**opts)
     if A_packed.dtype != torch.float64 or out.dtype != torch.float64:
         raise TypeError("A_packed and out must be float64 (complex data as interleaved pairs)")
@@ -353,8 +367,10 @@ def perm_batched(A_packed, sizes, offsets, is_complex: bool, out, status=None, s
     """Enqueue the batched permanents; results land in ``out`` (float64, 4 per matrix)."""
     import torch
     count = len(sizes)
-    n_arr = (ctypes.c_int32 * max(count, 1))(*[int(x) for x in sizes])
-    o_arr = (ctypes.c_int64 * max(count, 1))(*[int(x) for x in offsets])
+    if len(offsets) != count:
+        raise ValueError("sizes and offsets differ in length")
+    n_keep, n_arr = _host_ints(sizes, "int32")
+    o_keep, o_arr = _host_ints(offsets, "int64")
     o = make_opts(**opts)
     if A_packed.dtype != torch.float64 or out.dtype != torch.float64:
         raise TypeError("A_packed and out must be float64 (complex data as interleaved pairs)")

@@ -136,7 +136,8 @@ extern "C" perm_status perm_band(int dtype, const double* dA, const int32_t* h_n
   a.pad = 0;
   a.out = d_out;
   a.status = d_status;
-  int grid = o.blocks > 0 ? o.blocks : 8 * ws->cu_count;
+  int grid = o.blocks > 0 ? o.blocks
+                          : band_blocks_per_cu(dtype == PERM_DT_COMPLEX, k) * ws->cu_count;
   if (grid > count) grid = count;
   e = launch_band(dtype == PERM_DT_COMPLEX, k, a, grid, s);
   if (e != hipSuccess) return hip_fail("band launch", e);

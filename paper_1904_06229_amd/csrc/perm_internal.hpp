@@ -213,7 +213,7 @@ hipError_t launch_sparse_partition(int in_kind, const void* A, int n, int ld, in
 
 // ------------------------------------------------------------------ band ----
 // App. C transfer matrix (perm_band): one workgroup per matrix.
-constexpr int kBandMaxK = 5;  // 2^(2k+1) coefficients in LDS, double-buffered
+constexpr int kBandMaxK = 5;  // rank tables of 2^(2k+1) masks in LDS
 
 struct BandArgs {
   const double* A;        // matrices back to back (column-major, ld = n; complex pairs)
@@ -226,6 +226,8 @@ struct BandArgs {
 };
 
 hipError_t launch_band(bool cplx, int k, const BandArgs& a, int grid, hipStream_t s);
+// Workgroups of band_kernel<k> resident on one CU (occupancy query).
+int band_blocks_per_cu(bool cplx, int k);
 
 // Rows per exactly-multiplied group in the 0/1 walk: the largest k with
 // n^k < 2^50 (|2 w_i| <= n, so a group's product stays below 2^50).
