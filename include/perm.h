@@ -85,7 +85,9 @@ typedef struct {
   int32_t blocks;        /* workgroups of the main walk launch */
   float kernel_ms;       /* duration of the walk launches, from HIP events on `stream` */
   float total_ms;        /* duration of the whole call on `stream` (staging to result) */
-  int32_t walk_variant;  /* 0/1 path: 1 if the pair-shared walk ran (see perm_int01), else 0 */
+  int32_t walk_variant;  /* perm_int01: 1 if the pair-shared walk ran, else 0.  perm_sparse
+                            with PERM_DT_INT01: the row groups of the exact product (1..4),
+                            or 0 for the size-only grouping.  Otherwise 0 */
   int32_t col0_nonzeros; /* 0/1 path, pair-shared walk: ones in the column flipped between the
                             two terms of every pair; otherwise 0 */
 } perm_result;
@@ -244,10 +246,13 @@ perm_status perm_repeated_partial(int dtype, const double* dC, int n, int R, int
  *   out->terms is the number of sets; log2_chunk reports the inner digits.
  *   PERM_DT_INT01: exact.  The row sums are integers; every product is formed
  *   exactly in row groups and summed in 51-bit integer bins folded into a 128-bit
- *   integer (as perm_int01; chunks of at most 2^10 terms).  The result (int_lo/int_hi,
- *   and its nearest double pair in re_hi + re_lo) is exact when |per| < 2^127; the
- *   library checks Bregman's bound sum_i log2(d_i!)/d_i < 127 (d_i = row degrees) and
- *   returns PERM_ERANGE otherwise.  A zero row gives 0.
+ *   integer (as perm_int01; chunks of at most 2^10 terms).  A row sum is at most
+ *   the row's degree d_i, so the rows are dealt into the fewest (1..4) equal groups
+ *   whose products of degrees stay below 2^50 (out->walk_variant); when none
+ *   fits, groups of the largest k rows with n^k < 2^50, as in perm_int01.  The
+ *   result (int_lo/int_hi, and its nearest double pair in re_hi + re_lo) is exact
+ *   when |per| < 2^127; the library checks Bregman's bound sum_i log2(d_i!)/d_i < 127
+ *   and returns PERM_ERANGE otherwise.  A zero row gives 0.
  * Errors: PERM_EINVAL, PERM_ENONFINITE, PERM_ERANGE, PERM_ENOTIMPL (options other
  *   than log2_chunk <= 14, blocks, no_row_scaling), PERM_EHIP.
  */

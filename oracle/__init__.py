@@ -89,6 +89,7 @@ def _load():
         "oracle_sparse_real": ([dp, i, i, i, i, dp, up]),
         "oracle_sparse_int": ([bp, i, i, i, up, up]),
         "oracle_sparse_range": ([dp, i, i, i, u64, u64, i, dp]),
+        "oracle_sparse_range_int": ([bp, i, i, u64, u64, i, up]),
         "oracle_sparse_partition": ([dp, i, i, i, ctypes.POINTER(ctypes.c_int)]),
         "oracle_sparse_set": ([dp, i, i, i, u64, up]),
         "oracle_band_real": ([dp, i, i, i, i, dp]),
@@ -304,6 +305,19 @@ def sparse(A, threads: int = 0):
                                   ctypes.byref(terms)), "sparse")
     val = CPair(Pair(out[0], out[1]), Pair(out[2], out[3])) if cplx else Pair(out[0], out[1])
     return val, terms.value
+
+
+def sparse_range_int(A, g0: int, count: int, threads: int = 0) -> int:
+    """0/1 data: the raw App. B sum over Gray indices [g0, g0+count) of its
+    digit order, exact modulo 2^128 (as a signed int)."""
+    lib = _load()
+    M, n, kind = _prep(A)
+    if kind != "int":
+        raise TypeError("sparse_range_int takes a 0/1 (uint8) matrix")
+    out = (ctypes.c_uint64 * 2)()
+    _check(lib.oracle_sparse_range_int(_ptr(M, kind), n, max(n, 1), g0, count, threads, out),
+           "sparse_range_int")
+    return _words_to_int(out)
 
 
 def sparse_range(A, g0: int, count: int, threads: int = 0):

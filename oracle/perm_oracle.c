@@ -1264,6 +1264,21 @@ int oracle_sparse_range(const double* A, int n, int ld, int cplx, uint64_t g0, u
   return 0;
 }
 
+/* 0/1 data: the raw sum (no (-1)^n) over Gray indices [g0, g0 + count) as an
+ * integer modulo 2^128 (out[0] low word, out[1] high word). */
+int oracle_sparse_range_int(const uint8_t* B, int n, int ld, uint64_t g0, uint64_t count,
+                            int nthreads, uint64_t* out) {
+  long double re, im;
+  u128 acc;
+  uint64_t total;
+  if (count > (uint64_t)INT64_MAX) return -1;
+  int rc = sparse_run(NULL, B, n, ld, 0, 1, g0, (int64_t)count, nthreads, &re, &im, &acc,
+                      &total);
+  if (rc != 0) return -1;
+  u128_to_pair(acc, out);
+  return 0;
+}
+
 /* The partition: block_of_col[j] = block index (selection order) or -1 for
  * T; returns the number of blocks, or -1 (bad arguments / a zero row). */
 int oracle_sparse_partition(const double* A, int n, int ld, int cplx, int* block_of_col) {

@@ -224,8 +224,43 @@ __device__ __forceinline__ u128 exact_single(const MixArgs& a, uint64_t g) {
   return exact::fold(B);
 }
 
+// Exact product of the row sums into the bins.  KG = 0: groups of
+// int01_group_rows(N) rows (any 0/1 matrix).  KG >= 1: KG equal groups of
+// staged rows, each product formed by two interleaved chains; the caller has
+// ordered the rows so that every group's product of row degrees, which bounds
+// every partial product of the group, is below 2^50.
+template <int N, int KG, bool ADD>
+__device__ __forceinline__ void group_bins(const double (&r)[N], exact::Bins& B) {
+  if constexpr (KG == 0) {
+    exact::term_bins<N, ADD>(r, B);
+  } else {
+    constexpr int GS = (N + KG - 1) / KG;
+    double G[KG];
+#pragma unroll
+    for (int g = 0; g < KG; ++g) {
+      const int lo = g * GS, hi = (g + 1) * GS < N ? (g + 1) * GS : N;
+      double p0 = r[lo], p1 = lo + 1 < hi ? r[lo + 1] : 1.0;
+#pragma unroll
+      for (int i = lo + 2; i < hi; i += 2) {
+        p0 *= r[i];
+        if (i + 1 < hi) p1 *= r[i + 1];
+      }
+      G[g] = p0 * p1;
+    }
+    exact::product_bins<KG, ADD>(G, B);
+  }
+}
+
+template <int N, int KG>
+__device__ __forceinline__ exact::Bins group_offsets() {
+  if constexpr (KG == 0)
+    return exact::term_offsets<N>();
+  else
+    return exact::product_offsets<KG>();
+}
+
 // Exact integer sum of chunk c (L <= 2^10 terms, weights +-1 alternating).
-template <int N>
+template <int N, int KG>
 __device__ __forceinline__ u128 exact_chunk(const MixArgs& a, uint64_t c, uint32_t par) {
   const double* staged = opaque(a.staged);
   Rows<N> w;
@@ -243,14 +278,14 @@ __device__ __forceinline__ u128 exact_chunk(const MixArgs& a, uint64_t c, uint32
   int s = 0;
   for (; s + 1 < L; s += 2) {
     const int32_t o0 = toff[s], o1 = toff[s + 1];
-    exact::term_bins<N, true>(w.r, B);   // + P_s
+    group_bins<N, KG, true>(w.r, B);   // + P_s
     add_col<N>(w, staged, o0);
-    exact::term_bins<N, false>(w.r, B);  // - P_{s+1}
+    group_bins<N, KG, false>(w.r, B);  // - P_{s+1}
     add_col<N>(w, staged, o1);
   }
   if (s < L) {  // odd L: an unpaired + P_{L-1}
-    exact::term_bins<N, true>(w.r, B);
-    const exact::Bins off = exact::term_offsets<N>();
+    group_bins<N, KG, true>(w.r, B);
+    const exact::Bins off = group_offsets<N, KG>();
     B.b0 -= off.b0;
     B.b1 -= off.b1;
     B.b2 -= off.b2;
@@ -259,7 +294,7 @@ __device__ __forceinline__ u128 exact_chunk(const MixArgs& a, uint64_t c, uint32
   return ((tin[0] < 0.0) != (W < 0.0)) ? u128_neg(v) : v;
 }
 
-template <int N, bool SINGLE>
+template <int N, bool SINGLE, int KG>
 __global__ __launch_bounds__(kBlock) void mix_exact_kernel(MixArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint64_t wave = wave_id();
@@ -273,7 +308,7 @@ __global__ __launch_bounds__(kBlock) void mix_exact_kernel(MixArgs a) {
         part = exact_single<N>(a, a.first + c);
       } else {
         const uint32_t par = (uint32_t)((a.first + (task & 1)) & 1);
-        part = exact_chunk<N>(a, a.first + c, par);
+        part = exact_chunk<N, KG>(a, a.first + c, par);
       }
       if (c < a.nchunks) acc = u128_add(acc, part);
     }
@@ -331,16 +366,44 @@ __global__ __launch_bounds__(kBlock) void mix_walk_kernel(MixArgs a) {
 #endif
 }
 
+#if !PERM_CPLX
+// Row groups of the default exact product at size N.
 template <int N>
-hipError_t dispatch(bool single, bool exact, const MixArgs& a, int grid, hipStream_t s) {
+constexpr int default_groups() {
+  return (N + int01_group_rows(N) - 1) / int01_group_rows(N);
+}
+
+// The exact chunk walk with KG row groups; only KG below the default count
+// is instantiated (others fall back to the default grouping, always valid).
+template <int N, int KG>
+void launch_exact_groups(const MixArgs& a, int grid, hipStream_t s) {
+  if constexpr (KG < default_groups<N>())
+    hipLaunchKernelGGL((mix_exact_kernel<N, false, KG>), dim3(grid), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL((mix_exact_kernel<N, false, 0>), dim3(grid), dim3(kBlock), 0, s, a);
+}
+#endif
+
+template <int N>
+hipError_t dispatch(bool single, bool exact, int groups, const MixArgs& a, int grid,
+                    hipStream_t s) {
   if (exact) {
 #if PERM_CPLX
+    (void)groups;
     return hipErrorInvalidValue;
 #else
-    if (single)
-      hipLaunchKernelGGL((mix_exact_kernel<N, true>), dim3(grid), dim3(kBlock), 0, s, a);
-    else
-      hipLaunchKernelGGL((mix_exact_kernel<N, false>), dim3(grid), dim3(kBlock), 0, s, a);
+    static_assert(kMixMaxRowGroups == 4, "one case per group count");
+    if (single) {
+      hipLaunchKernelGGL((mix_exact_kernel<N, true, 0>), dim3(grid), dim3(kBlock), 0, s, a);
+    } else {
+      switch (groups) {
+        case 1: launch_exact_groups<N, 1>(a, grid, s); break;
+        case 2: launch_exact_groups<N, 2>(a, grid, s); break;
+        case 3: launch_exact_groups<N, 3>(a, grid, s); break;
+        case 4: launch_exact_groups<N, 4>(a, grid, s); break;
+        default: launch_exact_groups<N, 0>(a, grid, s); break;
+      }
+    }
     return hipGetLastError();
 #endif
   }
@@ -355,7 +418,7 @@ hipError_t dispatch(bool single, bool exact, const MixArgs& a, int grid, hipStre
 
 #define PERM_CASE(N) \
   case N:            \
-    return dispatch<N>(single, exact, a, grid, s);
+    return dispatch<N>(single, exact, groups, a, grid, s);
 
 // Built four times: PERM_CPLX selects real or complex, PERM_HALF the sizes
 // n = 1..32 or n = 33..64.
@@ -378,7 +441,7 @@ hipError_t dispatch(bool single, bool exact, const MixArgs& a, int grid, hipStre
 #define PERM_CASES "perm_cases_hi.inc"
 #endif
 
-hipError_t PERM_LAUNCH(int n, bool single, bool exact, const MixArgs& a, int grid,
+hipError_t PERM_LAUNCH(int n, bool single, bool exact, int groups, const MixArgs& a, int grid,
                        hipStream_t s) {
   switch (n) {
 #include PERM_CASES

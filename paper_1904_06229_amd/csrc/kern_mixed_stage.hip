@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kBlock) void stage_mix_kernel(const void* __restric
     bool bad = false;
     for (int c = 0; c < nc; ++c)
       for (int p = 0; p < cw; ++p) {
-        const double v = load_entry(A, in_kind, ld, i, dg.src[c], p);
+        const double v = load_entry(A, in_kind, ld, dg.row[i], dg.src[c], p);
         if (!isfinite(v)) bad = true;
         mx = fmax(mx, fabs(v));
       }
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kBlock) void stage_mix_kernel(const void* __restric
       double ss = 0.0;  // squared 2-norm of row i of the matrix, over mx^2
       for (int c = 0; c < nc; ++c)
         for (int p = 0; p < cw; ++p) {
-          const double v = load_entry(A, in_kind, ld, i, dg.src[c], p) / mx;
+          const double v = load_entry(A, in_kind, ld, dg.row[i], dg.src[c], p) / mx;
           ss += (double)dg.cmult[c] * v * v;
         }
       int q;
@@ -109,7 +109,8 @@ __global__ __launch_bounds__(kBlock) void stage_mix_kernel(const void* __restric
   for (int idx = tid; idx < cols; idx += kBlock) {
     const int i = idx % n, c = idx / n;
     for (int p = 0; p < cw; ++p) {
-      const double v = c < nc ? ldexp(load_entry(A, in_kind, ld, i, dg.src[c], p), s_exp[i]) : 0.0;
+      const double v =
+          c < nc ? ldexp(load_entry(A, in_kind, ld, dg.row[i], dg.src[c], p), s_exp[i]) : 0.0;
       staged[cw * idx + p] = v;
       staged[cw * (cols + idx) + p] = c < nc ? -v : 0.0;
     }
@@ -318,6 +319,7 @@ __global__ __launch_bounds__(kBlock) void sparse_partition_kernel(const void* __
     out->log2_degprod = ldp;
     out->bregman = breg;
   }
+  if (tid < n) out->deg[tid] = s_deg[tid];
 }
 
 }  // namespace

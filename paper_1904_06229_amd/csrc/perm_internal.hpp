@@ -149,6 +149,7 @@ struct MixDigits {
   int32_t mult[kMaxN];    // kind 0: multiplicity m
   int32_t src[kMaxN];     // staged column c is source column src[c]
   int32_t cmult[kMaxN];   // copies of staged column c in the matrix (row-norm weight)
+  int32_t row[kMaxN];     // staged row i is source row row[i]
 };
 
 // Device copy of the digit description, read with scalar loads by the walk:
@@ -181,16 +182,21 @@ hipError_t launch_mix_stage(int in_kind, const void* A, int n, int ld, const Mix
                             int32_t* rowexp, int32_t* status, hipStream_t s);
 // single: every lane sums one term (Gray indices first .. first + nchunks - 1).
 // exact (real only; 0/1 data with weights +-1, L <= 2^10): 128-bit integer
-// partials instead of double-double ones.
+// partials instead of double-double ones.  groups (exact chunk walk only):
+// 0 multiplies the rows in groups of int01_group_rows(n), valid for any 0/1
+// matrix; 1..kMixMaxRowGroups splits the staged rows into that many equal
+// groups (ceil(n / groups) rows, the last shorter), which the caller has
+// checked keep every group's product of row degrees below 2^50.
 constexpr int kMixExactMaxLog2Chunk = 10;
-hipError_t launch_mix_walk_real_lo(int n, bool single, bool exact, const MixArgs& a, int grid,
-                                   hipStream_t s);
-hipError_t launch_mix_walk_real_hi(int n, bool single, bool exact, const MixArgs& a, int grid,
-                                   hipStream_t s);
-hipError_t launch_mix_walk_complex_lo(int n, bool single, bool exact, const MixArgs& a, int grid,
-                                      hipStream_t s);
-hipError_t launch_mix_walk_complex_hi(int n, bool single, bool exact, const MixArgs& a, int grid,
-                                      hipStream_t s);
+constexpr int kMixMaxRowGroups = 4;
+hipError_t launch_mix_walk_real_lo(int n, bool single, bool exact, int groups, const MixArgs& a,
+                                   int grid, hipStream_t s);
+hipError_t launch_mix_walk_real_hi(int n, bool single, bool exact, int groups, const MixArgs& a,
+                                   int grid, hipStream_t s);
+hipError_t launch_mix_walk_complex_lo(int n, bool single, bool exact, int groups,
+                                      const MixArgs& a, int grid, hipStream_t s);
+hipError_t launch_mix_walk_complex_hi(int n, bool single, bool exact, int groups,
+                                      const MixArgs& a, int grid, hipStream_t s);
 
 // App. B greedypartition on the device.  Trial 0 takes the lowest row index
 // among rows of least degree; trials 1.. break ties with a counter-based hash
@@ -206,6 +212,7 @@ struct SparsePart {
   double log2_terms;      // log2 of 2^|T| prod (2^|S| - 1)
   double log2_degprod;    // log2 prod_i (nonzeros of row i)
   double bregman;         // sum_i log2(d_i!) / d_i: log2 of Bregman's bound on |per| (0/1 data)
+  int32_t deg[kMaxN];     // d_i, the nonzeros of row i
 };
 
 hipError_t launch_sparse_partition(int in_kind, const void* A, int n, int ld, int trials,

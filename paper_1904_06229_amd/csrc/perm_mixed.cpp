@@ -10,6 +10,7 @@
 // wait -> (-1)^n and the row scaling.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -125,13 +126,53 @@ perm_status get_ws(MixWorkspace** out) {
 
 int floor_log2(uint64_t x) { return x ? 63 - __builtin_clzll(x) : -1; }
 
-hipError_t launch_walk(bool cplx, int n, bool single, bool exact, const MixArgs& a, int grid,
-                       hipStream_t s) {
+hipError_t launch_walk(bool cplx, int n, bool single, bool exact, int groups, const MixArgs& a,
+                       int grid, hipStream_t s) {
   if (cplx)
-    return n <= 32 ? launch_mix_walk_complex_lo(n, single, exact, a, grid, s)
-                   : launch_mix_walk_complex_hi(n, single, exact, a, grid, s);
-  return n <= 32 ? launch_mix_walk_real_lo(n, single, exact, a, grid, s)
-                 : launch_mix_walk_real_hi(n, single, exact, a, grid, s);
+    return n <= 32 ? launch_mix_walk_complex_lo(n, single, exact, groups, a, grid, s)
+                   : launch_mix_walk_complex_hi(n, single, exact, groups, a, grid, s);
+  return n <= 32 ? launch_mix_walk_real_lo(n, single, exact, groups, a, grid, s)
+                 : launch_mix_walk_real_hi(n, single, exact, groups, a, grid, s);
+}
+
+// Exact 0/1 products: deal the rows into kg equal groups (ceil(n / kg) rows,
+// the last shorter) so that every group's product of row degrees is below
+// 2^50.  A row sum of a 0/1 matrix over any column set is at most the row's
+// degree, so every partial product of a group is then an exact double.  Rows
+// are taken by decreasing degree, each into the open group with the smallest
+// log-degree sum; row[] lists group 0's rows, then group 1's, ...  Returns
+// false when some group's product reaches 2^50.
+bool group_rows(const int32_t* deg, int n, int kg, int32_t* row) {
+  const int gs = (n + kg - 1) / kg;
+  if (kg < 1 || kg > kMixMaxRowGroups || (kg - 1) * gs >= n) return false;
+  int order[kMaxN];
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order, order + n, [&](int x, int y) { return deg[x] > deg[y]; });
+  double lsum[kMixMaxRowGroups] = {};
+  int cnt[kMixMaxRowGroups] = {};
+  int member[kMixMaxRowGroups][kMaxN];
+  for (int q = 0; q < n; ++q) {
+    const int i = order[q];
+    int best = -1;
+    for (int g = 0; g < kg; ++g) {
+      const int cap = g + 1 < kg ? gs : n - (kg - 1) * gs;
+      if (cnt[g] < cap && (best < 0 || lsum[g] < lsum[best])) best = g;
+    }
+    member[best][cnt[best]++] = i;
+    lsum[best] += std::log2((double)(deg[i] > 0 ? deg[i] : 1));
+  }
+  int k = 0;
+  for (int g = 0; g < kg; ++g) {
+    uint64_t prod = 1;
+    std::sort(member[g], member[g] + cnt[g]);
+    for (int t = 0; t < cnt[g]; ++t) {
+      const uint64_t d = (uint64_t)(deg[member[g][t]] > 0 ? deg[member[g][t]] : 1);
+      prod *= d;  // stays below 2^50 * 64 before the check fails
+      if (prod >= (1ull << 50)) return false;
+      row[k++] = member[g][t];
+    }
+  }
+  return true;
 }
 
 // The options the mixed-radix walks take: precision PERM_FP64_DD, log2_chunk
@@ -160,7 +201,8 @@ struct Walked {
 // exact: 128-bit integer sums (0/1 data, weights +-1).
 perm_status run_mixed(MixWorkspace* ws, int in_kind, const void* dA, int n, int ld,
                       const MixDigits& dg, uint64_t start, uint64_t count, const perm_opts& o,
-                      int row_scaling, bool exact, hipStream_t stream, Walked* wk) {
+                      int row_scaling, bool exact, int groups, hipStream_t stream,
+                      Walked* wk) {
   const bool cplx = in_kind == 1;
   // Inner digits: as many leading digits as fit in the chunk cap (at least one).
   int cap_lg = o.log2_chunk;
@@ -214,7 +256,7 @@ perm_status run_mixed(MixWorkspace* ws, int in_kind, const void* dA, int n, int 
     const int grid = (int)blocks;
     if (grid_out) *grid_out = grid;
     nparts += grid;
-    const hipError_t e = launch_walk(cplx, n, single, exact, a, grid, stream);
+    const hipError_t e = launch_walk(cplx, n, single, exact, groups, a, grid, stream);
     if (e != hipSuccess) return hip_fail("mixed-radix walk launch", e);
     return PERM_OK;
   };
@@ -281,6 +323,7 @@ perm_status rep_call(int dtype, const double* dC, int n, int R, int ld, const in
   if (!dC || !mult) return set_error(PERM_EINVAL, "NULL argument");
   MixDigits dg;
   std::memset(&dg, 0, sizeof dg);
+  for (int i = 0; i < n; ++i) dg.row[i] = i;
   dg.R = R;
   dg.ncols = R;
   int total = 0;
@@ -319,7 +362,7 @@ perm_status rep_call(int dtype, const double* dC, int n, int R, int ld, const in
   if ((st = get_ws(&ws)) != PERM_OK) return st;
   Walked wk;
   st = run_mixed(ws, dtype == PERM_DT_COMPLEX ? 1 : 0, dC, n, ld, dg, start, count, o,
-                 o.no_row_scaling ? 0 : 1, false, stream, &wk);
+                 o.no_row_scaling ? 0 : 1, false, 0, stream, &wk);
   if (st != PERM_OK) return st;
   fill_float(wk, (whole && (n % 2)) ? -1.0 : 1.0, count, &r);  // per = (-1)^n S
   *out = r;
@@ -354,6 +397,7 @@ perm_status partition(MixWorkspace* ws, int dtype, const void* dA, int n, int ld
 // Digits of the sparse enumeration: blocks (kind 1), then the columns of T.
 void sparse_digits(const SparsePart& p, int n, MixDigits* dg) {
   std::memset(dg, 0, sizeof *dg);
+  for (int i = 0; i < n; ++i) dg->row[i] = i;
   int c = 0, d = 0;
   for (int l = 0; l < p.nblocks; ++l, ++d) {
     dg->kind[d] = 1;
@@ -414,11 +458,21 @@ perm_status sparse_call(int dtype, const void* dA, int n, int ld, int trials, ui
     return PERM_OK;
   }
   Walked wk;
+  int groups = 0;  // exact: the fewest row groups whose degree products fit
+  if (exact) {
+    const int k = int01_group_rows(n);
+    const int kdef = (n + k - 1) / k;
+    for (int kg = 1; kg < kdef && kg <= kMixMaxRowGroups && !groups; ++kg)
+      if (group_rows(p.deg, n, kg, dg.row)) groups = kg;
+    if (!groups)
+      for (int i = 0; i < n; ++i) dg.row[i] = i;
+  }
   st = run_mixed(ws, in_kind_of(dtype), dA, n, ld, dg, start, count, o,
-                 (exact || o.no_row_scaling) ? 0 : 1, exact, stream, &wk);
+                 (exact || o.no_row_scaling) ? 0 : 1, exact, groups, stream, &wk);
   if (st != PERM_OK) return st;
   fill_float(wk, (whole && (n % 2)) ? -1.0 : 1.0, count, &r);
   if (exact) {
+    r.walk_variant = groups;
     // S = sum over the sets of (-1)^|J| prod_i r_i modulo 2^128; per = (-1)^n S
     unsigned __int128 u = ((unsigned __int128)wk.res.iw[1] << 64) | wk.res.iw[0];
     if (whole && (n % 2)) u = (unsigned __int128)0 - u;

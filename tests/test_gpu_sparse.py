@@ -132,6 +132,30 @@ def test_int01_band_shaped_n64_against_band_oracle(B, orc):
     assert got.exact == want
 
 
+@pytest.mark.parametrize("n,p,seed,groups", [(40, 0.02, 1, 1), (40, 0.06, 2, 2), (40, 0.15, 3, 3),
+                                             (48, 0.2, 4, 4), (48, 0.5, 5, 0)])
+def test_int01_row_groups_exact(B, orc, n, p, seed, groups):
+    """The exact walk deals the rows into the fewest equal groups (1..4) whose
+    products of row degrees stay below 2^50, else falls back to groups of the
+    size-only bound (0).  Each grouping against the oracle's exact integer
+    range sums (mod 2^128), on ragged ranges at both ends and inside."""
+    A = sparse_matrix(n, p, seed, "int")
+    dA = dev(A)
+    bits = float(np.log2(A.sum(axis=1)).sum())
+    _, _, T = B.perm_sparse_partition(dA)
+    count = (1 << 14) + 37
+    r = np.random.default_rng(seed)
+    for start in [0, T - count] + [int(x) for x in r.integers(0, T - count, size=3)]:
+        got = B.perm_sparse_partial(dA, start, count)
+        assert got.walk_variant == groups, (got.walk_variant, groups)
+        assert groups == 0 or bits < 50 * groups
+        want = orc.sparse_range_int(A, start, count)
+        assert got.exact == want, (n, p, start)
+    if T < 1 << 24:
+        assert B.perm_sparse(dA).exact == orc.sparse(A)[0]
+    log(f"0/1 n={n} p={p}: log2 prod deg {bits:.0f}, {groups} row groups, 2^{math.log2(T):.1f} sets")
+
+
 @pytest.mark.parametrize("seed", range(5))
 def test_partition_matches_oracle(B, orc, seed):
     for n, p in ((12, 0.2), (30, 0.06), (64, 0.02)):

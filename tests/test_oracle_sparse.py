@@ -139,3 +139,38 @@ def test_exact_integers_identity_plus_bernoulli(orc):
     for n, p in ((16, 0.05), (20, 0.1), (22, 0.02)):
         A = sparse_matrix(n, p, n, "int")
         assert orc.sparse(A)[0] == orc.ryser(A)
+
+
+def _wrap128(v):
+    v %= 1 << 128
+    return v - (1 << 128) if v >= 1 << 127 else v
+
+
+def test_exact_integer_ranges(orc):
+    """sparse_range_int: the 0/1 range sum modulo 2^128.  Ranges add up to the
+    whole sum, (-1)^n per(A) from the exact integer Ryser; single terms equal
+    (-1)^|J| prod_i (ones of row i in J) formed here with Python integers for
+    the set J of that Gray index, also where the products pass 2^64 (where a
+    long-double sum would round)."""
+    n = 13
+    A = sparse_matrix(n, 0.25, 21, "int")
+    _, terms = orc.sparse(A)
+    cuts = [0, 1, 5, terms // 2, terms // 2 + 3, terms]
+    tot = sum(orc.sparse_range_int(A, a, b - a) for a, b in zip(cuts, cuts[1:]))
+    assert _wrap128(tot) == _wrap128((-1) ** n * orc.ryser(A))
+    for n, p, seed in ((13, 0.25, 21), (30, 0.5, 3), (40, 0.6, 4)):
+        A = sparse_matrix(n, p, seed, "int")
+        Af = A.astype(np.float64)
+        blocks = partition_blocks(orc.sparse_partition(Af))
+        T = 2 ** (n - sum(len(S) for S in blocks)) * math.prod(2 ** len(S) - 1 for S in blocks)
+        r = np.random.default_rng(seed)
+        for g in [0, 1, 2, T - 1] + [int(x) for x in r.integers(0, T, size=5)]:
+            J = orc.sparse_set(Af, g)
+            cols = [j for j in range(n) if (J >> j) & 1]
+            prod = 1
+            for i in range(n):
+                prod *= int(sum(int(A[i, j]) for j in cols))
+            want = _wrap128((-1) ** len(cols) * prod)
+            assert orc.sparse_range_int(A, g, 1) == want, (n, g)
+        if n > 13:
+            assert prod > 1 << 64 or prod == 0
