@@ -37,9 +37,11 @@
 // row is computed; the rows' entries alternate between two LDS slots, so one
 // barrier per row suffices.  Powers of two keep long products in range,
 // exactly: each row's entries are scaled into [1/2, 1); and every 4 rows the
-// threads publish the largest magnitude of the coefficients they wrote, which
-// the next row applies, as a power of two, to the values it produces (one row
-// late, no barrier of its own).  The exponents are restored at the end.  The
+// threads publish the largest binary exponent of the coefficients they wrote,
+// which the next row applies to the values it produces (one row late, no
+// barrier of its own).  Both maxima are taken over frexp exponents with DPP
+// lane permutes and lane reads, which keeps LDS round trips off the row's
+// critical path.  The exponents are restored at the end.  The
 // final coefficient sum is a fixed-order double-double reduction.
 #include "perm_device.hpp"
 #include "perm_internal.hpp"
@@ -52,6 +54,33 @@ __host__ __device__ constexpr int binom_c(int n, int r) {
   int v = 1;
   for (int t = 1; t <= r; ++t) v = v * (n - r + t) / t;
   return v;
+}
+
+// Binary exponent of x (frexp: x = f 2^e, 1/2 <= |f| < 1), or kNoExp for 0.
+// The exponent of the largest magnitude is the largest exponent.
+constexpr int kNoExp = INT32_MIN;
+__device__ __forceinline__ int exponent(double x) {
+  int e = 0;
+  frexp(x, &e);
+  return x != 0.0 ? e : kNoExp;
+}
+
+// Maximum over the 16 lanes of each row of the wave, by DPP lane permutes
+// (VALU only, no LDS round trip): quad swaps, then the half-row and row mirrors.
+__device__ __forceinline__ int row16_max(int v) {
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));  // row_mirror
+  return v;
+}
+
+// Maximum over the wave (uniform): the four rows' maxima read from lanes 0, 16, 32, 48.
+__device__ __forceinline__ int wave_max_int(int v) {
+  v = row16_max(v);
+  const int a = max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16));
+  const int b = max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48));
+  return max(a, b);
 }
 
 template <bool CPLX>
@@ -75,13 +104,14 @@ __global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
   constexpr int NTOP = NC - NT;             // interior masks with it
   static_assert(NT <= kBlock && NTOP <= kBlock, "one mask of each kind per thread");
   static_assert(NC < 65536, "ranks are 16-bit");
+  static_assert(TOP < 16, "a row's entries sit in the first 16 lanes of wave 0");
   constexpr int cw = CPLX ? 2 : 1;
   using C = Coef<CPLX>;
   __shared__ C s_c[2][NC];           // coefficients of the live class, by rank
   __shared__ uint16_t s_rank[S];     // rank of a mask in its popcount class
   __shared__ uint16_t s_cls[S];      // masks grouped by popcount, ascending in a group
   __shared__ C s_a[2][TOP + 1];      // scaled band entries of a row, by row parity
-  __shared__ double s_mx[kWavesPerBlock];
+  __shared__ int s_mx[kWavesPerBlock];  // largest coefficient exponent per wave
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
@@ -149,9 +179,10 @@ __global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
       if (wave == 0) {  // row i's scale, and its entries into this row's LDS slot
         const bool nf = !isfinite(vr) || !isfinite(vi);
         bad = bad || __ballot(nf) != 0;
-        const double mx = wave_max(fmax(fabs(vr), fabs(vi)));
-        int e = 0;
-        if (mx > 0.0 && !bad) frexp(mx, &e);  // scale the row by 2^-e
+        // the exponent of the row's largest entry, from lanes 0..15
+        const int emx = __builtin_amdgcn_readfirstlane(
+            row16_max(max(exponent(vr), exponent(vi))));
+        const int e = (emx != kNoExp && !bad) ? emx : 0;  // scale the row by 2^-e
         esum += e;
         if (lane <= TOP) {
           s_a[ab][lane].re = ldexp(vr, -e);
@@ -164,23 +195,23 @@ __global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
       // the class maximum published by row i-1, applied to this row's output
       int ex = 0;
       if (i > 0 && (i & 3) == 0) {
-        double Mx = s_mx[0];
+        int Mx = s_mx[0];
 #pragma unroll
-        for (int w = 1; w < kWavesPerBlock; ++w) Mx = fmax(Mx, s_mx[w]);
-        if (Mx > 0.0 && isfinite(Mx)) frexp(Mx, &ex);
+        for (int w = 1; w < kWavesPerBlock; ++w) Mx = max(Mx, s_mx[w]);
+        ex = Mx != kNoExp ? Mx : 0;
         esum += ex;
       }
       const C* old = s_c[cur];
       C* nw = s_c[cur ^ 1];
       const C* ar = s_a[ab];
-      double lm = 0.0;
+      int lm = kNoExp;  // largest exponent among this thread's outputs
       auto put = [&](int r, double xr, double xi) {
         C v;
         v.re = ldexp(xr, -ex);
-        lm = fmax(lm, fabs(v.re));
+        lm = max(lm, exponent(v.re));
         if constexpr (CPLX) {
           v.im = ldexp(xi, -ex);
-          lm = fmax(lm, fabs(v.im));
+          lm = max(lm, exponent(v.im));
         }
         nw[r] = v;
       };
@@ -227,8 +258,8 @@ __global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
           put(r - c0, xr_acc, xi_acc);
         }
       }
-      if ((i & 3) == 3) {  // publish the class maximum for row i+1
-        lm = wave_max(lm);
+      if ((i & 3) == 3) {  // publish the class's largest exponent for row i+1
+        lm = wave_max_int(lm);
         if (lane == 0) s_mx[wave] = lm;
       }
       cur ^= 1;
