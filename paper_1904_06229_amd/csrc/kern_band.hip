@@ -94,6 +94,67 @@ struct Coef<false> {
   double re;
 };
 
+// One interior row (i > k: b0 = 1, class k+1 before and after) for the
+// thread's two masks.  Coefficients come from buffer P and the row's entries
+// from slot P (P = i mod 2, fixed at compile time so that every LDS address is
+// a loop-invariant register plus a constant); the results go to buffer P ^ 1,
+// scaled by 2^-ex.  When pub is set, returns the largest exponent written.
+template <int K, bool CPLX, int P>
+__device__ __forceinline__ int interior_row(Coef<CPLX> (*s_c)[binom_c(2 * K + 1, K + 1)],
+                                            const Coef<CPLX> (*s_a)[2 * K + 2],
+                                            const uint32_t (&src_nt)[K + 1], uint32_t src_top,
+                                            int tid, int ex, bool pub) {
+  constexpr int W = 2 * K + 1;
+  constexpr int TOP = W;
+  constexpr int NC = binom_c(W, K + 1);
+  constexpr int NT = binom_c(W - 1, K + 1);
+  constexpr int NTOP = NC - NT;
+  using C = Coef<CPLX>;
+  const C* old = s_c[P];
+  C* nw = s_c[P ^ 1];
+  const C* ar = s_a[P];
+  int lm = kNoExp;
+  auto put = [&](int r, double xr, double xi) {
+    C v;
+    v.re = xr;
+    if constexpr (CPLX) v.im = xi;
+    if (ex != 0) {  // uniform: the renormalisation row
+      v.re = ldexp(v.re, -ex);
+      if constexpr (CPLX) v.im = ldexp(v.im, -ex);
+    }
+    if (pub) {  // uniform: the row that publishes the class's exponent
+      lm = max(lm, exponent(v.re));
+      if constexpr (CPLX) lm = max(lm, exponent(v.im));
+    }
+    nw[r] = v;
+  };
+  if (tid < NT) {
+    double xr_acc = 0.0, xi_acc = 0.0;
+#pragma unroll
+    for (int t = 0; t <= K; ++t) {
+      const C x = old[src_nt[t] & 0xffff];
+      const C av = ar[src_nt[t] >> 16];
+      xr_acc = fma(x.re, av.re, xr_acc);
+      if constexpr (CPLX) {
+        xr_acc = fma(-x.im, av.im, xr_acc);
+        xi_acc = fma(x.re, av.im, fma(x.im, av.re, xi_acc));
+      }
+    }
+    put(tid, xr_acc, xi_acc);
+  }
+  if (tid < NTOP) {
+    const C x = old[src_top];
+    const C av = ar[TOP];
+    double xr_acc = x.re * av.re, xi_acc = 0.0;
+    if constexpr (CPLX) {
+      xr_acc = fma(-x.im, av.im, xr_acc);
+      xi_acc = fma(x.re, av.im, x.im * av.re);
+    }
+    put(NT + tid, xr_acc, xi_acc);
+  }
+  return lm;
+}
+
 template <int K, bool CPLX>
 __global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
   constexpr int W = 2 * K + 1;              // window columns
@@ -159,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
       s_c[0][0].re = 1.0;
       if constexpr (CPLX) s_c[0][0].im = 0.0;
     }
-    int cur = 0, esum = 0;
+    int esum = 0;
     bool bad = false;
     // Lane c of wave 0 holds the entry of column i-k-1+c (c = 1..2k+1) of row i.
     double vr = 0.0, vi = 0.0;
@@ -174,9 +235,11 @@ __global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
       }
     };
     if (wave == 0) load_entry(0);
-    for (int i = 0; i < n; ++i) {
-      const int ab = i & 1;
-      if (wave == 0) {  // row i's scale, and its entries into this row's LDS slot
+    // Start of row i: wave 0 scales the row's entries into slot i mod 2 and
+    // loads row i+1's; the barrier; then the class exponent published by row
+    // i-1 (on renormalisation rows), uniform.
+    auto head = [&](int i) -> int {
+      if (wave == 0) {
         const bool nf = !isfinite(vr) || !isfinite(vi);
         bad = bad || __ballot(nf) != 0;
         // the exponent of the row's largest entry, from lanes 0..15
@@ -185,14 +248,13 @@ __global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
         const int e = (emx != kNoExp && !bad) ? emx : 0;  // scale the row by 2^-e
         esum += e;
         if (lane <= TOP) {
-          s_a[ab][lane].re = ldexp(vr, -e);
-          if constexpr (CPLX) s_a[ab][lane].im = ldexp(vi, -e);
+          s_a[i & 1][lane].re = ldexp(vr, -e);
+          if constexpr (CPLX) s_a[i & 1][lane].im = ldexp(vi, -e);
         }
         if (i + 1 < n) load_entry(i + 1);  // in flight during row i
       }
       // one barrier: row i's entries, and row i-1's coefficients, are in LDS
       __syncthreads();
-      // the class maximum published by row i-1, applied to this row's output
       int ex = 0;
       if (i > 0 && (i & 3) == 0) {
         int Mx = s_mx[0];
@@ -201,69 +263,63 @@ __global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
         ex = Mx != kNoExp ? Mx : 0;
         esum += ex;
       }
-      const C* old = s_c[cur];
-      C* nw = s_c[cur ^ 1];
-      const C* ar = s_a[ab];
-      int lm = kNoExp;  // largest exponent among this thread's outputs
-      auto put = [&](int r, double xr, double xi) {
-        C v;
-        v.re = ldexp(xr, -ex);
-        lm = max(lm, exponent(v.re));
-        if constexpr (CPLX) {
-          v.im = ldexp(xi, -ex);
-          lm = max(lm, exponent(v.im));
-        }
-        nw[r] = v;
-      };
-      if (i > K) {  // interior row
-        if (tid < NT) {
-          double xr_acc = 0.0, xi_acc = 0.0;
-#pragma unroll
-          for (int t = 0; t <= K; ++t) {
-            const C x = old[src_nt[t] & 0xffff];
-            const C av = ar[src_nt[t] >> 16];
-            xr_acc = fma(x.re, av.re, xr_acc);
-            if constexpr (CPLX) {
-              xr_acc = fma(-x.im, av.im, xr_acc);
-              xi_acc = fma(x.re, av.im, fma(x.im, av.re, xi_acc));
-            }
-          }
-          put(tid, xr_acc, xi_acc);
-        }
-        if (tid < NTOP) {
-          const C x = old[src_top];
-          const C av = ar[TOP];
-          double xr_acc = x.re * av.re, xi_acc = 0.0;
-          if constexpr (CPLX) {
-            xr_acc = fma(-x.im, av.im, xr_acc);
-            xi_acc = fma(x.re, av.im, x.im * av.re);
-          }
-          put(NT + tid, xr_acc, xi_acc);
-        }
-      } else {  // rows 0..k: class i+1 over b0 = 0, sources in class i
-        const int c0 = cstart[i + 1], c1 = cstart[i + 2];
-        for (int r = c0 + tid; r < c1; r += kBlock) {
-          const int Q = s_cls[r] << 1;
-          double xr_acc = 0.0, xi_acc = 0.0;
-          for (int q = (Q >> TOP) & 1 ? (1 << TOP) : Q; q; q &= q - 1) {
-            const int c = __ffs(q) - 1;
-            const C x = old[s_rank[Q ^ (1 << c)]];
-            const C av = ar[c];
-            xr_acc = fma(x.re, av.re, xr_acc);
-            if constexpr (CPLX) {
-              xr_acc = fma(-x.im, av.im, xr_acc);
-              xi_acc = fma(x.re, av.im, fma(x.im, av.re, xi_acc));
-            }
-          }
-          put(r - c0, xr_acc, xi_acc);
-        }
-      }
-      if ((i & 3) == 3) {  // publish the class's largest exponent for row i+1
+      return __builtin_amdgcn_readfirstlane(ex);
+    };
+    // End of row i: every 4 rows, publish the class's largest exponent for row i+1.
+    auto tail = [&](int i, int lm) {
+      if ((i & 3) == 3) {
         lm = wave_max_int(lm);
         if (lane == 0) s_mx[wave] = lm;
       }
-      cur ^= 1;
+    };
+    // rows 0..k: class i+1 over b0 = 0, sources in class i (ranks from the table)
+    const int ng = n < K + 1 ? n : K + 1;
+    for (int i = 0; i < ng; ++i) {
+      const int ex = head(i);
+      const C* old = s_c[i & 1];
+      C* nw = s_c[(i & 1) ^ 1];
+      const C* ar = s_a[i & 1];
+      int lm = kNoExp;
+      const int c0 = cstart[i + 1], c1 = cstart[i + 2];
+      for (int r = c0 + tid; r < c1; r += kBlock) {
+        const int Q = s_cls[r] << 1;
+        double xr_acc = 0.0, xi_acc = 0.0;
+        for (int q = (Q >> TOP) & 1 ? (1 << TOP) : Q; q; q &= q - 1) {
+          const int c = __ffs(q) - 1;
+          const C x = old[s_rank[Q ^ (1 << c)]];
+          const C av = ar[c];
+          xr_acc = fma(x.re, av.re, xr_acc);
+          if constexpr (CPLX) {
+            xr_acc = fma(-x.im, av.im, xr_acc);
+            xi_acc = fma(x.re, av.im, fma(x.im, av.re, xi_acc));
+          }
+        }
+        C v;
+        v.re = ldexp(xr_acc, -ex);
+        lm = max(lm, exponent(v.re));
+        if constexpr (CPLX) {
+          v.im = ldexp(xi_acc, -ex);
+          lm = max(lm, exponent(v.im));
+        }
+        nw[r - c0] = v;
+      }
+      tail(i, lm);
     }
+    // interior rows, two at a time so that the buffer parity is a constant
+    constexpr int P0 = (K + 1) & 1;
+    int i = K + 1;
+    for (; i + 1 < n; i += 2) {
+      int ex = head(i);
+      tail(i, interior_row<K, CPLX, P0>(s_c, s_a, src_nt, src_top, tid, ex, (i & 3) == 3));
+      ex = head(i + 1);
+      tail(i + 1, interior_row<K, CPLX, P0 ^ 1>(s_c, s_a, src_nt, src_top, tid, ex,
+                                                 ((i + 1) & 3) == 3));
+    }
+    if (i < n) {
+      const int ex = head(i);
+      tail(i, interior_row<K, CPLX, P0>(s_c, s_a, src_nt, src_top, tid, ex, (i & 3) == 3));
+    }
+    const int cur = n & 1;  // the buffer row n-1 wrote
     __syncthreads();
     // set every remaining x_j = 1: the sum of the class's coefficients, fixed order
     const int pl = n < K + 1 ? n : K + 1;
