@@ -285,21 +285,23 @@ perm_status perm_sparse_partition(int dtype, const void* dA, int n, int ld, int 
  * the transfer matrix of App. C (bandpermanent), one workgroup per matrix.
  *   per(A) is the sum of the coefficients of prod_i (sum_j a_ij x_j) with every
  *   x_j^2 = 0; after row i the variable of column i-k-1 is set to 1, so only
- *   the 2^(2k+1) monomials over columns i-k..i+k are kept.  n * 2^(2k+1) * O(k)
- *   operations per matrix, no inclusion-exclusion and so no cancellation beyond
- *   that of the entries themselves.
+ *   the monomials over columns i-k..i+k are kept, and of those only the ones with
+ *   min(i+1, k+1) columns can reach the end (at most binom(2k+1, k+1) of them).
+ *   O(n * binom(2k+1, k+1) * k) operations per matrix, no inclusion-exclusion and so
+ *   no cancellation beyond that of the entries themselves.
  *   dtype    PERM_DT_REAL or PERM_DT_COMPLEX.
  *   dA       device array, matrices back to back; matrix m starts at element offset
  *            h_offset[m] (in doubles) and is column-major with ld = n_m (complex:
  *            interleaved pairs).  Entries with |i - j| > k are not read: the result is
  *            the permanent of the band part.
  *   h_n      HOST array of sizes, 1 <= n_m <= 65536; h_offset HOST array of offsets.
- *   k        0 <= k <= 5 (the coefficients live in LDS).
+ *   k        0 <= k <= 5 (the coefficients and the 2^(2k+1)-entry rank table live in LDS).
  *   d_out    device array, 4 doubles per matrix: re_hi, re_lo, im_hi, im_lo (each row is
  *            scaled by a power of two during the product and the scale is restored at the
  *            end; values beyond the double range come back as +-inf).
  *   d_status device array of count int32 (may be NULL): PERM_OK or PERM_ENONFINITE.
- * Options: only `blocks` (workgroups; 0 = 8 per CU).  Waits for `stream`.
+ * Options: only `blocks` (workgroups; 0 = as many as fit on the device at once, from the
+ * occupancy of the kernel for k).  Waits for `stream`.
  * Errors: PERM_EINVAL, PERM_ENOTIMPL (other options), PERM_ENOMEM, PERM_EHIP.
  */
 perm_status perm_band(int dtype, const double* dA, const int32_t* h_n, const int64_t* h_offset,
