@@ -80,10 +80,19 @@ typedef const __attribute__((address_space(4))) BatchItem* citem_ptr;
 typedef const __attribute__((address_space(4))) int64_t* ci64_ptr;
 typedef const __attribute__((address_space(4))) int32_t* ci32_ptr;
 
+// Smallest waves per SIMD the compiler must keep for size N: up to n = 24
+// the walk fits 4 waves (128 VGPRs) with at most a few spills outside the
+// chunk loop, where it would otherwise take a few registers more and run
+// with 3; larger sizes keep the compiler's choice.
+template <int N>
+constexpr int batched_min_waves() {
+  return N <= 24 ? 4 : 1;
+}
+
 // The items [item0, item0 + nitems), all of size N.
 template <int N, int MODE, bool CPLX>
-__global__ __launch_bounds__(kBlock) void batched_size_kernel(BatchArgs a, uint64_t item0,
-                                                              uint64_t nitems) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(batched_min_waves<N>())))
+void batched_size_kernel(BatchArgs a, uint64_t item0, uint64_t nitems) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint64_t wave = wave_id();
   const uint64_t nwaves = (uint64_t)gridDim.x * kWavesPerBlock;
