@@ -21,24 +21,35 @@ namespace {
 
 __device__ __forceinline__ bool finite(double x) { return isfinite(x); }
 
+// The matrix is first copied into LDS with coalesced loads (all threads), so
+// the per-row statistics read LDS instead of walking a row of global memory
+// one dependent load at a time.
 __global__ __launch_bounds__(kBlock) void stage_float_kernel(const double* __restrict__ A, int n,
                                                              int ld, int is_complex,
                                                              int row_scaling, double* staged,
                                                              double* rowabs, int32_t* rowexp,
                                                              int32_t* status) {
+  __shared__ double s_a[2 * kMaxN * kMaxN];  // column-major, ld = n (complex: pairs)
   __shared__ int32_t s_exp[kMaxN];
   __shared__ int32_t s_bad;
   const int tid = threadIdx.x;
   if (tid == 0) s_bad = 0;
-  __syncthreads();
   const int cw = is_complex ? 2 : 1;  // doubles per entry
+  const int nn = n * n;
+  const int tot = cw * nn;
+  for (int t = tid; t < tot; t += kBlock) {
+    const int idx = t / cw, c = t - cw * (t / cw);
+    const int i = idx % n, j = idx / n;
+    s_a[t] = A[cw * ((size_t)i + (size_t)j * ld) + c];
+  }
+  __syncthreads();
   if (tid < n) {
     const int i = tid;
     double mx = 0.0;
     bool bad = false;
     for (int j = 0; j < n; ++j) {
       for (int c = 0; c < cw; ++c) {
-        const double v = A[cw * ((size_t)i + (size_t)j * ld) + c];
+        const double v = s_a[cw * (i + j * n) + c];
         if (!finite(v)) bad = true;
         mx = fmax(mx, fabs(v));
       }
@@ -48,7 +59,7 @@ __global__ __launch_bounds__(kBlock) void stage_float_kernel(const double* __res
       double ss = 0.0;
       for (int j = 0; j < n; ++j)
         for (int c = 0; c < cw; ++c) {
-          const double v = A[cw * ((size_t)i + (size_t)j * ld) + c] / mx;
+          const double v = s_a[cw * (i + j * n) + c] / mx;
           ss += v * v;
         }
       int k;
@@ -61,22 +72,19 @@ __global__ __launch_bounds__(kBlock) void stage_float_kernel(const double* __res
     if (bad) atomicOr(&s_bad, 1);
   }
   __syncthreads();
-  const int nn = n * n;
-  for (int idx = tid; idx < nn; idx += kBlock) {
-    const int i = idx % n, j = idx / n;
-    for (int c = 0; c < cw; ++c) {
-      const double v = ldexp(A[cw * ((size_t)i + (size_t)j * ld) + c], s_exp[i]);
-      staged[cw * idx + c] = v;
-      staged[cw * (nn + idx) + c] = -v;
-    }
+  for (int t = tid; t < tot; t += kBlock) {
+    const int i = (t / cw) % n;
+    const double v = ldexp(s_a[t], s_exp[i]);
+    staged[t] = v;
+    staged[tot + t] = -v;
   }
-  __syncthreads();
   if (tid < n) {
     const int i = tid;
+    const int e = s_exp[i];
     double s = 0.0;
     for (int j = 0; j < n; ++j) {
-      const size_t o = (size_t)cw * (i + (size_t)j * n);
-      s += is_complex ? hypot(staged[o], staged[o + 1]) : fabs(staged[o]);
+      const int o = cw * (i + j * n);
+      s += is_complex ? hypot(ldexp(s_a[o], e), ldexp(s_a[o + 1], e)) : fabs(ldexp(s_a[o], e));
     }
     rowabs[i] = 0.5 * s;
   }
