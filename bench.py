@@ -61,13 +61,24 @@ KERNEL_SOURCES = {
 }
 
 
+def _strip_comments(src: str) -> str:
+    """C/C++ source without its comments and blank lines (the kernel sources
+    hold no string literal containing comment markers)."""
+    import re
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return "\n".join(line.rstrip() for line in src.splitlines() if line.strip())
+
+
 def source_sha(kind):
+    """Hash of the code (comments excluded) that a walk kernel is built from:
+    a counter summary stays valid across comment edits, not code edits."""
     import hashlib
     base = os.path.join(ROOT, "paper_1904_06229_amd", "csrc")
     h = hashlib.sha256()
     for f in KERNEL_SOURCES[kind] + ["perm_device.hpp", "perm_internal.hpp"]:
-        with open(os.path.join(base, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(base, f), encoding="utf-8") as fh:
+            h.update(_strip_comments(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

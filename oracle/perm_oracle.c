@@ -500,7 +500,7 @@ typedef struct {
   u128 acc;
 } chunk_job;
 
-/* Row-sum vector of App. A (subpermanent, steps 5-7) for Gray code x:
+/* Row-sum vector of App. A (subpermanent) for Gray code x:
  *   w_i = a_{i,n} - 1/2 sum_{j=1..n} a_{ij} + sum_{j<n, x_j = 1} a_{ij}
  * (columns and bits 0-based here: bit j of x stands for column j). */
 static void* chunk_real_worker(void* arg) {

@@ -237,7 +237,7 @@ __device__ __forceinline__ void prod_c32(const double (&wr)[N], const double (&w
 }
 
 // ------------------------------------------------------------ row sums ----
-// Start vector of a chunk (App. A, subpermanent steps 5-7, written as
+// Start vector of a chunk (App. A, subpermanent, written as
 // w_i = 1/2 (a_{i,n} + sum_{j<n} delta_j a_ij), delta_j = 2 x_j - 1), formed
 // directly from the staged +A for the Gray code of term index g.
 
