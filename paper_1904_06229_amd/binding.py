@@ -331,11 +331,18 @@ def perm_sparse_partition(A, trials: int = 1, seed: int = 0, stream=None):
 
 def _host_ints(seq, dtype):
     """A C-contiguous host array of `dtype` holding `seq` (zero-copy for a
-    matching numpy array) and its address, for the size/offset arguments."""
+    matching numpy array) and its address, for the size/offset arguments.
+    Values outside `dtype` raise instead of wrapping."""
     import numpy as np
-    arr = np.ascontiguousarray(np.asarray(seq, dtype=dtype))
-    if arr.ndim != 1:
+    raw = np.asarray(seq)
+    if raw.ndim != 1:
         raise ValueError("sizes and offsets must be one-dimensional")
+    if raw.size and raw.dtype.kind not in "iu":
+        raise TypeError("sizes and offsets must be integers")
+    info = np.iinfo(dtype)
+    if raw.size and (int(raw.min()) < info.min or int(raw.max()) > info.max):
+        raise ValueError(f"a size or offset does not fit {np.dtype(dtype).name}")
+    arr = np.ascontiguousarray(raw.astype(dtype, copy=False))
     if arr.size == 0:
         arr = np.zeros(1, dtype=dtype)
     return arr, ctypes.c_void_p(arr.ctypes.data)

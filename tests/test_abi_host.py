@@ -109,3 +109,19 @@ def test_int01_bound_thresholds(b):
     from paper_1904_06229_amd import inputs
     B = inputs.bernoulli01(30, 20190413)
     assert b.perm_int01_bound(B.sum(axis=1)) < 120
+
+
+def test_size_offset_arrays_checked(b):
+    """Sizes and offsets reach the library as int32 / int64 arrays without a
+    per-element copy; a value that does not fit raises instead of wrapping."""
+    arr, ptr = b._host_ints(np.arange(5, dtype=np.int64), "int32")
+    assert arr.dtype == np.int32 and list(arr) == [0, 1, 2, 3, 4] and ptr.value
+    same = np.arange(3, dtype=np.int64)
+    assert np.shares_memory(b._host_ints(same, "int64")[0], same)  # no copy
+    for bad in ([2 ** 40], np.array([2 ** 33], dtype=np.int64), [-(2 ** 31) - 1]):
+        with pytest.raises(ValueError):
+            b._host_ints(bad, "int32")
+    with pytest.raises(TypeError):
+        b._host_ints([1.5], "int32")
+    with pytest.raises(ValueError):
+        b._host_ints([[1, 2]], "int64")
