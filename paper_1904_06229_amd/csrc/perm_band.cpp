@@ -27,6 +27,7 @@ struct BandWorkspace {
   size_t cap = 0;           // matrices the buffers hold
   char* dmem = nullptr;     // n (int32) then offsets (int64)
   char* hmem = nullptr;     // pinned staging, same layout
+  int blocks_per_cu[2][kBandMaxK + 1] = {};  // occupancy by (complex, k); 0 = not queried
 };
 
 std::mutex g_mu;
@@ -136,8 +137,9 @@ extern "C" perm_status perm_band(int dtype, const double* dA, const int32_t* h_n
   a.pad = 0;
   a.out = d_out;
   a.status = d_status;
-  int grid = o.blocks > 0 ? o.blocks
-                          : band_blocks_per_cu(dtype == PERM_DT_COMPLEX, k) * ws->cu_count;
+  int& per_cu = ws->blocks_per_cu[dtype == PERM_DT_COMPLEX ? 1 : 0][k];
+  if (per_cu == 0) per_cu = band_blocks_per_cu(dtype == PERM_DT_COMPLEX, k);
+  int grid = o.blocks > 0 ? o.blocks : per_cu * ws->cu_count;
   if (grid > count) grid = count;
   e = launch_band(dtype == PERM_DT_COMPLEX, k, a, grid, s);
   if (e != hipSuccess) return hip_fail("band launch", e);
