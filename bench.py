@@ -12,7 +12,7 @@ Printed: one JSON line with the throughput, the roofline of the walk kernel
 issue peak; the kernel's own duration comes from HIP events recorded by the
 library on the launch stream), and the CPU oracle timed on the host cores.
 
-Other workloads (--workload c1|c3|c5|c4|c6) are for manual runs; c5 (48x48
+Other workloads (--workload c1|c3|c4|c5|c6|c7|c8) are for manual runs; c5 (48x48
 real, 2^47 terms, minutes per permanent) runs as 16 perm_partial slices with
 a progress line each; c6 is the repeated-column path (Eq. ryser2) on a
 48-photon output with two photons in each of 24 modes; c7 is the band
