@@ -104,8 +104,10 @@ def profiled_traffic(kernel, kind):
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=20)
-    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--steps", type=int, default=None,
+                   help="timed steps (default 20; 1 for a whole sliced permanent)")
+    p.add_argument("--warmup", type=int, default=None,
+                   help="untimed steps first (default 3; 0 for a whole sliced permanent)")
     p.add_argument("--workload", default="c2",
                    choices=["c1", "c2", "c3", "c4", "c5", "c6", "c7", "c8"])
     p.add_argument("--count", type=int, default=100000, help="c4: number of matrices")
@@ -123,7 +125,20 @@ def parse():
                    help="time only the first 2^K Gray terms (perm_partial); labelled as a prefix")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run a plain 256 MiB device copy (scale reference for HBM counters)")
-    return p.parse_args()
+    args = p.parse_args()
+    # A whole 48 x 48 permanent (minutes) is one step by default; a checkpoint
+    # resumes one permanent, so it allows exactly one step and no warmup.
+    sliced = bool(args.slices or args.checkpoint or
+                  (args.workload == "c5" and not args.terms_log2))
+    if args.checkpoint and ((args.steps or 1) != 1 or (args.warmup or 0) != 0):
+        p.error("--checkpoint resumes one permanent: it takes --steps 1 --warmup 0")
+    if args.steps is None:
+        args.steps = 1 if sliced else 20
+    if args.warmup is None:
+        args.warmup = 0 if sliced else 3
+    if args.steps < 1 or args.warmup < 0:
+        p.error("--steps must be >= 1 and --warmup >= 0")
+    return args
 
 
 def make_workload(name):
@@ -509,7 +524,7 @@ def bench_sliced(args):
     def prog(m):
         print(m, file=sys.stderr, flush=True)
 
-    kms, value, t_all = [], None, 0.0
+    kms, value, t_all, run_slices = [], None, 0.0, 0
     for step in range(args.warmup + args.steps):
         prog(f"step {step + 1}/{args.warmup + args.steps} ({'warmup' if step < args.warmup else 'timed'})")
         torch.cuda.synchronize()
@@ -521,8 +536,14 @@ def bench_sliced(args):
         if step >= args.warmup:
             t_all += dt
             kms.extend(info["kernel_ms"])
+            run_slices += len(info["kernel_ms"])
     terms = 2 ** (n - 1)
-    per_perm = n * float(terms)
+    if run_slices == 0:  # a checkpoint that was already complete: nothing was timed
+        print(json.dumps({"error": "the checkpoint already holds every slice; nothing was timed",
+                          "result": repr(value)}))
+        sys.exit(3)
+    # throughput over the slices evaluated in this run (all of them without a checkpoint)
+    per_perm = n * float(terms) * run_slices / (slices * args.steps)
     alg = algorithmic_ops_per_term(kind, n) * float(terms) / slices
     kavg = sum(kms) / len(kms) if kms else float("nan")
     if isinstance(value, tuple):
@@ -537,7 +558,8 @@ def bench_sliced(args):
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": desc + f", whole permanent as {slices} slices of "
                                       f"{terms // slices} terms",
-                   "n": n, "terms": terms, "slices": slices, "precision": args.precision},
+                   "n": n, "terms": terms, "slices": slices, "precision": args.precision,
+                   "slices_timed": run_slices, "resumed": args.steps * slices - run_slices},
         "roofline": {"bound": "alu", "achieved": alg / (kavg * 1e-3) / 1e12,
                      "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
                      "frac": alg / (kavg * 1e-3) / PEAK_LANE_OPS,

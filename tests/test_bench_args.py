@@ -1,0 +1,39 @@
+"""bench.py's step defaults (CPU only; nothing is run).
+
+A whole sliced permanent (the 48 x 48 workload: minutes per step) is timed
+once by default, and a checkpoint, which resumes one permanent, allows only
+that single step: further steps would resume a complete checkpoint and time
+no work.
+"""
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def parse(argv, monkeypatch):
+    monkeypatch.setattr(sys, "argv", ["bench.py", *argv])
+    a = bench.parse()
+    return a.steps, a.warmup
+
+
+def test_defaults(monkeypatch):
+    assert parse([], monkeypatch) == (20, 3)
+    assert parse(["--workload", "c3"], monkeypatch) == (20, 3)
+    assert parse(["--workload", "c5", "--terms-log2", "30"], monkeypatch) == (20, 3)
+    assert parse(["--workload", "c5"], monkeypatch) == (1, 0)
+    assert parse(["--slices", "4"], monkeypatch) == (1, 0)
+    assert parse(["--workload", "c5", "--checkpoint", "ck.jsonl"], monkeypatch) == (1, 0)
+    assert parse(["--steps", "5", "--warmup", "0"], monkeypatch) == (5, 0)
+
+
+@pytest.mark.parametrize("argv", [["--workload", "c5", "--checkpoint", "c", "--steps", "2"],
+                                  ["--workload", "c5", "--checkpoint", "c", "--warmup", "1"],
+                                  ["--steps", "0"], ["--warmup", "-1"]])
+def test_rejected(argv, monkeypatch):
+    with pytest.raises(SystemExit):
+        parse(argv, monkeypatch)
