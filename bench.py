@@ -105,9 +105,11 @@ def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=None,
-                   help="timed steps (default 20; 1 for a whole sliced permanent)")
+                   help="timed steps (default 20; c3, c4, c8: 5, 3, 3; c6: 10; 1 for a whole "
+                        "sliced permanent)")
     p.add_argument("--warmup", type=int, default=None,
-                   help="untimed steps first (default 3; 0 for a whole sliced permanent)")
+                   help="untimed steps first (default 3; c3, c4, c6, c8: 1; 0 for a whole "
+                        "sliced permanent)")
     p.add_argument("--workload", default="c2",
                    choices=["c1", "c2", "c3", "c4", "c5", "c6", "c7", "c8"])
     p.add_argument("--count", type=int, default=100000, help="c4: number of matrices")
@@ -132,10 +134,15 @@ def parse():
                   (args.workload == "c5" and not args.terms_log2))
     if args.checkpoint and ((args.steps or 1) != 1 or (args.warmup or 0) != 0):
         p.error("--checkpoint resumes one permanent: it takes --steps 1 --warmup 0")
+    # defaults keep the timed work of a manual run near a minute or less
+    steps, warmup = {"c3": (5, 1), "c4": (3, 1), "c6": (10, 1), "c8": (3, 1)}.get(
+        args.workload, (20, 3))
+    if sliced:
+        steps, warmup = 1, 0
     if args.steps is None:
-        args.steps = 1 if sliced else 20
+        args.steps = steps
     if args.warmup is None:
-        args.warmup = 0 if sliced else 3
+        args.warmup = warmup
     if args.steps < 1 or args.warmup < 0:
         p.error("--steps must be >= 1 and --warmup >= 0")
     return args

@@ -23,7 +23,8 @@ def parse(argv, monkeypatch):
 
 def test_defaults(monkeypatch):
     assert parse([], monkeypatch) == (20, 3)
-    assert parse(["--workload", "c3"], monkeypatch) == (20, 3)
+    assert parse(["--workload", "c3"], monkeypatch) == (5, 1)
+    assert parse(["--workload", "c8"], monkeypatch) == (3, 1)
     assert parse(["--workload", "c5", "--terms-log2", "30"], monkeypatch) == (20, 3)
     assert parse(["--workload", "c5"], monkeypatch) == (1, 0)
     assert parse(["--slices", "4"], monkeypatch) == (1, 0)
