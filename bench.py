@@ -12,12 +12,13 @@ Printed: one JSON line with the throughput, the roofline of the walk kernel
 issue peak; the kernel's own duration comes from HIP events recorded by the
 library on the launch stream), and the CPU oracle timed on the host cores.
 
-Other workloads (--workload c1|c3|c4|c5|c6|c7|c8) are for manual runs; c5 (48x48
+Other workloads (--workload c1|c3|c4|c5|c6|c7|c8|c9) are for manual runs; c5 (48x48
 real, 2^47 terms, minutes per permanent) runs as 16 perm_partial slices with
 a progress line each; c6 is the repeated-column path (Eq. ryser2) on a
 48-photon output with two photons in each of 24 modes; c7 is the band
 transfer matrix (App. C) on a batch of 64 x 64 band matrices; c8 the exact
-sparse path (App. B) on the paper's identity + Bernoulli(p) matrices.
+sparse path (App. B) on the paper's identity + Bernoulli(p) matrices; c9 the
+random-ensemble study (Sec. III) on 100000 Ginibre 20 x 20 matrices.
 """
 from __future__ import annotations
 
@@ -111,7 +112,7 @@ def parse():
                    help="untimed steps first (default 3; c3, c4, c6, c8: 1; 0 for a whole "
                         "sliced permanent)")
     p.add_argument("--workload", default="c2",
-                   choices=["c1", "c2", "c3", "c4", "c5", "c6", "c7", "c8"])
+                   choices=["c1", "c2", "c3", "c4", "c5", "c6", "c7", "c8", "c9"])
     p.add_argument("--count", type=int, default=100000, help="c4: number of matrices")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-autotune", action="store_true",
@@ -135,7 +136,7 @@ def parse():
     if args.checkpoint and ((args.steps or 1) != 1 or (args.warmup or 0) != 0):
         p.error("--checkpoint resumes one permanent: it takes --steps 1 --warmup 0")
     # defaults keep the timed work of a manual run near a minute or less
-    steps, warmup = {"c3": (5, 1), "c4": (3, 1), "c6": (10, 1), "c8": (3, 1)}.get(
+    steps, warmup = {"c3": (5, 1), "c4": (3, 1), "c6": (10, 1), "c8": (3, 1), "c9": (5, 1)}.get(
         args.workload, (20, 3))
     if sliced:
         steps, warmup = 1, 0
@@ -514,6 +515,89 @@ def bench_sparse(args):
     print(json.dumps(out))
 
 
+def bench_ensemble(args):
+    """The random-ensemble study of Sec. III on the device: 100000 Ginibre
+    20 x 20 matrices (resident in HBM before the timed region); a step is the
+    batched permanents of all of them (perm_batched, graph replay) and the
+    statistics of X = |per A| / sqrt(n!): its first four moments and F(x) on
+    the 16-per-decade grid."""
+    import numpy as np
+    import torch
+    from paper_1904_06229_amd import binding as B, ensembles, inputs
+
+    n, seed = 20, 20190405
+    count = args.count
+    mats = inputs.ensemble_batch("gaussian", n, count, seed)
+    cm = np.ascontiguousarray(np.transpose(mats, (0, 2, 1))).astype(np.complex128)
+    dA = torch.from_numpy(cm.ravel().view(np.float64)).to("cuda")
+    sizes = np.full(count, n, dtype=np.int32)
+    offs = np.arange(count, dtype=np.int64) * (2 * n * n)
+    out = torch.zeros(4 * count, dtype=torch.float64, device="cuda")
+    st = torch.zeros(count, dtype=torch.int32, device="cuda")
+    t1 = time.perf_counter()
+    if not args.no_autotune:
+        B.perm_autotune(True, n, n)
+    tune_s = time.perf_counter() - t1
+    xg = ensembles.grid(1e-3, 10.0)
+    norm = 1.0 / math.sqrt(math.factorial(n))
+    s = torch.cuda.Stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(s):
+        kms, mom, F = [], None, None
+        for step in range(args.warmup + args.steps):
+            if step == args.warmup:
+                s.synchronize()
+                t0 = time.perf_counter()
+            ev0.record(s)
+            B.perm_batched(dA, sizes, offs, True, out, st, stream=s, use_graph=True)
+            ev1.record(s)
+            o = out.view(count, 4)
+            X = torch.complex(o[:, 0] + o[:, 1], o[:, 2] + o[:, 3]).abs() * norm
+            mom = ensembles.moments(X)
+            F = ensembles.cdf(X, xg)
+            if step >= args.warmup:
+                kms.append(ev0.elapsed_time(ev1))
+        s.synchronize()
+        dt = time.perf_counter() - t0
+    assert int((st != 0).sum()) == 0
+    kavg = sum(kms) / len(kms)
+    ops = algorithmic_ops_per_term("complex", n) * 2.0 ** (n - 1) * count
+    o = {
+        "metric": "ensemble permanents/s (Sec. III study)",
+        "value": args.steps * count / dt, "unit": "permanents/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{count} Ginibre {n}x{n} matrices (entries (g1 + i g2)/sqrt(2)), "
+                               f"seed {seed}; per step: perm_batched + moments + F(x) on "
+                               f"{len(xg)} grid points", "n": n, "count": count,
+                   "autotune_s": round(tune_s, 2)},
+        "roofline": {"bound": "alu", "achieved": ops / (kavg * 1e-3) / 1e12,
+                     "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
+                     "frac": ops / (kavg * 1e-3) / PEAK_LANE_OPS, "traffic": None,
+                     "kernel": "batched stage+walk+finish (graph)", "kernel_ms": kavg},
+        "moments_X": mom, "F_at_1": float(F[np.argmin(np.abs(xg - 1.0))]),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        t2 = time.perf_counter()
+        done, worst = 0, 0.0
+        res = out.view(count, 4).cpu().numpy()
+        while time.perf_counter() - t2 < 10.0 and done < count:
+            w = oracle.ryser(mats[done])
+            want = complex(w.re.hi + w.re.lo, w.im.hi + w.im.lo)
+            got = complex(res[done, 0] + res[done, 1], res[done, 2] + res[done, 3])
+            worst = max(worst, abs(got - want) / abs(want))
+            done += 1
+        cdt = time.perf_counter() - t2
+        o["cpu_baseline"] = {"value": done / cdt, "unit": "permanents/s",
+                             "cores": oracle.default_threads(), "kind": "oracle",
+                             "sample": f"first {done} matrices of the batch (long-double Ryser)",
+                             "seconds": round(cdt, 2), "max_rel_err_vs_gpu": worst}
+    print(json.dumps(o))
+
+
 def bench_sliced(args):
     """Each step is one whole permanent as consecutive perm_partial slices
     (a progress line per slice on stderr); slice sums are added in slice order."""
@@ -593,6 +677,8 @@ def main():
         return bench_band(args)
     if args.workload == "c8":
         return bench_sparse(args)
+    if args.workload == "c9":
+        return bench_ensemble(args)
     if args.slices or args.checkpoint or (args.workload == "c5" and not args.terms_log2):
         return bench_sliced(args)
     import numpy as np

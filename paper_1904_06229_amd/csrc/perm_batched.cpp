@@ -387,9 +387,12 @@ perm_status perm_autotune(int is_complex, int n_lo, int n_hi, const char* cache_
     return set_error(PERM_EHIP, "hipEventCreate failed");
   perm_status result = PERM_OK;
   for (int n = n_lo; n <= n_hi && result == PERM_OK; ++n) {
-    // Synthetic batch: enough matrices for about 2^25 terms (at least 64).
+    // Synthetic batch: enough matrices for about 2^30 terms (at least 64, at
+    // most 16384), so that every chunk length is timed on a grid that fills the
+    // device several times over, as a large batch does (a small batch favours
+    // short chunks, which a large one pays for in chunk starts).
     const int64_t per = 1ll << (n - 1);
-    int count = (int)std::min<int64_t>(4096, std::max<int64_t>(64, (1ll << 25) / per));
+    int count = (int)std::min<int64_t>(16384, std::max<int64_t>(64, (1ll << 30) / per));
     const size_t elems = (size_t)count * n * n * cw;
     std::vector<double> h(elems);
     uint64_t x = 0x9E3779B97F4A7C15ull ^ (uint64_t)n;
