@@ -282,7 +282,7 @@ perm_status perm_sparse_partition(int dtype, const void* dA, int n, int ld, int 
 
 /*
  * perm_band -- permanents of band matrices (a_ij = 0 whenever |i - j| > k) by
- * the transfer matrix of App. C (bandpermanent), one workgroup per matrix.
+ * the transfer matrix of App. C (bandpermanent), one wavefront per matrix.
  *   per(A) is the sum of the coefficients of prod_i (sum_j a_ij x_j) with every
  *   x_j^2 = 0; after row i the variable of column i-k-1 is set to 1, so only
  *   the monomials over columns i-k..i+k are kept, and of those only the ones with
@@ -300,8 +300,9 @@ perm_status perm_sparse_partition(int dtype, const void* dA, int n, int ld, int 
  *            scaled by a power of two during the product and the scale is restored at the
  *            end; values beyond the double range come back as +-inf).
  *   d_status device array of count int32 (may be NULL): PERM_OK or PERM_ENONFINITE.
- * Options: only `blocks` (workgroups; 0 = as many as fit on the device at once, from the
- * occupancy of the kernel for k).  Waits for `stream`.
+ * Options: only `blocks` (workgroups of four wavefronts, one matrix per wavefront at a
+ * time; 0 = as many as fit on the device at once, from the occupancy of the kernel for k,
+ * and no more than the batch needs).  Waits for `stream`.
  * Errors: PERM_EINVAL, PERM_ENOTIMPL (other options), PERM_ENOMEM, PERM_EHIP.
  */
 perm_status perm_band(int dtype, const double* dA, const int32_t* h_n, const int64_t* h_offset,

@@ -27,22 +27,23 @@
 //
 // For the interior rows (i > k: b0 = 1, p = k+1 before and after) the sources
 // of a mask do not depend on i.  The class's masks without column i+k come
-// first in rank order (they are the smaller numbers); thread t owns the t-th
-// of them (k+1 sources) and the t-th of the others (one source), and keeps
-// their source ranks and columns in registers for the whole launch.  The
-// first k+1 rows, where the class grows, look the ranks up in LDS.
+// first in rank order (they are the smaller numbers); lane l owns the masks
+// l, l+64, ... of each kind (k+1 sources for the first kind, one for the
+// second) and keeps their source ranks and columns in registers for the whole
+// launch.  The first k+1 rows, where the class grows, look the ranks up in LDS.
 //
-// One workgroup per matrix (grid-stride over the batch).  Wave 0 loads the
-// next row's 2k+1 band entries (one per lane, vector loads) while the current
-// row is computed; the rows' entries alternate between two LDS slots, so one
-// barrier per row suffices.  Powers of two keep long products in range,
-// exactly: each row's entries are scaled into [1/2, 1); and every 4 rows the
-// threads publish the largest binary exponent of the coefficients they wrote,
-// which the next row applies to the values it produces (one row late, no
-// barrier of its own).  Both maxima are taken over frexp exponents with DPP
-// lane permutes and lane reads, which keeps LDS round trips off the row's
-// critical path.  The exponents are restored at the end.  The
-// final coefficient sum is a fixed-order double-double reduction.
+// One wavefront per matrix, four per workgroup, each with its own pair of
+// coefficient buffers and its own row slot; the rank tables are shared.  A row
+// then needs no barrier: a wave's LDS accesses are served in order, so a
+// compiler fence between rows suffices.  Lane c loads entry c of the next row
+// (vector loads) while the current row is computed.  Powers of two keep long
+// products in range, exactly: each row's entries are scaled into [1/2, 1); and
+// every 4 rows the wave takes the largest binary exponent of the coefficients
+// it wrote, which the next row applies to the values it produces (one row
+// late, off the row's critical path).  Both maxima are taken over frexp
+// exponents with DPP lane permutes and lane reads, which keeps LDS round trips
+// off the row.  The exponents are restored at the end.  The final coefficient
+// sum is a fixed-order double-double reduction.
 #include "perm_device.hpp"
 #include "perm_internal.hpp"
 
@@ -94,25 +95,35 @@ struct Coef<false> {
   double re;
 };
 
+// Sizes of the live class for half-width K.
+template <int K>
+struct Shape {
+  static constexpr int W = 2 * K + 1;              // window columns
+  static constexpr int S = 1 << W;                 // masks
+  static constexpr int TOP = W;                    // bit of column i+k in Q
+  static constexpr int NC = binom_c(W, K + 1);     // largest class
+  static constexpr int NT = binom_c(W - 1, K + 1); // interior masks without column i+k
+  static constexpr int NTOP = NC - NT;             // interior masks with it
+  // of the first kind per lane (at least one slot: k = 0 has none)
+  static constexpr int JN = NT > 0 ? (NT + kWave - 1) / kWave : 1;
+  static constexpr int JT = (NTOP + kWave - 1) / kWave;  // of the second kind per lane
+};
+
 // One interior row (i > k: b0 = 1, class k+1 before and after) for the
-// thread's two masks.  Coefficients come from buffer P and the row's entries
-// from slot P (P = i mod 2, fixed at compile time so that every LDS address is
-// a loop-invariant register plus a constant); the results go to buffer P ^ 1,
-// scaled by 2^-ex.  When pub is set, returns the largest exponent written.
+// lane's masks.  Coefficients come from buffer P of the wave's pair (P = i
+// mod 2, fixed at compile time so that every LDS address is a loop-invariant
+// register plus a constant); the results go to buffer P ^ 1, scaled by
+// 2^-ex.  When pub is set, returns the largest exponent written.
 template <int K, bool CPLX, int P>
-__device__ __forceinline__ int interior_row(Coef<CPLX> (*s_c)[binom_c(2 * K + 1, K + 1)],
-                                            const Coef<CPLX> (*s_a)[2 * K + 2],
-                                            const uint32_t (&src_nt)[K + 1], uint32_t src_top,
-                                            int tid, int ex, bool pub) {
-  constexpr int W = 2 * K + 1;
-  constexpr int TOP = W;
-  constexpr int NC = binom_c(W, K + 1);
-  constexpr int NT = binom_c(W - 1, K + 1);
-  constexpr int NTOP = NC - NT;
+__device__ __forceinline__ int interior_row(Coef<CPLX> (*sc)[Shape<K>::NC],
+                                            const Coef<CPLX>* ar,
+                                            const uint32_t (&src_nt)[Shape<K>::JN][K + 1],
+                                            const uint32_t (&src_top)[Shape<K>::JT], int lane,
+                                            int ex, bool pub) {
+  using Sh = Shape<K>;
   using C = Coef<CPLX>;
-  const C* old = s_c[P];
-  C* nw = s_c[P ^ 1];
-  const C* ar = s_a[P];
+  const C* old = sc[P];
+  C* nw = sc[P ^ 1];
   int lm = kNoExp;
   auto put = [&](int r, double xr, double xi) {
     C v;
@@ -128,58 +139,69 @@ __device__ __forceinline__ int interior_row(Coef<CPLX> (*s_c)[binom_c(2 * K + 1,
     }
     nw[r] = v;
   };
-  if (tid < NT) {
-    double xr_acc = 0.0, xi_acc = 0.0;
 #pragma unroll
-    for (int t = 0; t <= K; ++t) {
-      const C x = old[src_nt[t] & 0xffff];
-      const C av = ar[src_nt[t] >> 16];
-      xr_acc = fma(x.re, av.re, xr_acc);
-      if constexpr (CPLX) {
-        xr_acc = fma(-x.im, av.im, xr_acc);
-        xi_acc = fma(x.re, av.im, fma(x.im, av.re, xi_acc));
+  for (int jj = 0; jj < Sh::JN; ++jj) {
+    const int r = lane + kWave * jj;
+    if (r < Sh::NT) {
+      double xr_acc = 0.0, xi_acc = 0.0;
+#pragma unroll
+      for (int t = 0; t <= K; ++t) {
+        const C x = old[src_nt[jj][t] & 0xffff];
+        const C av = ar[src_nt[jj][t] >> 16];
+        xr_acc = fma(x.re, av.re, xr_acc);
+        if constexpr (CPLX) {
+          xr_acc = fma(-x.im, av.im, xr_acc);
+          xi_acc = fma(x.re, av.im, fma(x.im, av.re, xi_acc));
+        }
       }
+      put(r, xr_acc, xi_acc);
     }
-    put(tid, xr_acc, xi_acc);
   }
-  if (tid < NTOP) {
-    const C x = old[src_top];
-    const C av = ar[TOP];
-    double xr_acc = x.re * av.re, xi_acc = 0.0;
-    if constexpr (CPLX) {
-      xr_acc = fma(-x.im, av.im, xr_acc);
-      xi_acc = fma(x.re, av.im, x.im * av.re);
+  const C at = ar[Sh::TOP];
+#pragma unroll
+  for (int jj = 0; jj < Sh::JT; ++jj) {
+    const int r = lane + kWave * jj;
+    if (r < Sh::NTOP) {
+      const C x = old[src_top[jj]];
+      double xr_acc = x.re * at.re, xi_acc = 0.0;
+      if constexpr (CPLX) {
+        xr_acc = fma(-x.im, at.im, xr_acc);
+        xi_acc = fma(x.re, at.im, x.im * at.re);
+      }
+      put(Sh::NT + r, xr_acc, xi_acc);
     }
-    put(NT + tid, xr_acc, xi_acc);
   }
   return lm;
 }
 
+// A wave's LDS writes are visible to its own later LDS reads (the LDS serves a
+// wave's instructions in order); this keeps the compiler from moving reads of
+// one row above the writes of the previous one.
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 template <int K, bool CPLX>
 __global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
-  constexpr int W = 2 * K + 1;              // window columns
-  constexpr int S = 1 << W;                 // masks
-  constexpr int TOP = W;                    // bit of column i+k in Q
-  constexpr int NC = binom_c(W, K + 1);     // largest class
-  constexpr int NT = binom_c(W - 1, K + 1); // interior masks without column i+k
-  constexpr int NTOP = NC - NT;             // interior masks with it
-  static_assert(NT <= kBlock && NTOP <= kBlock, "one mask of each kind per thread");
-  static_assert(NC < 65536, "ranks are 16-bit");
-  static_assert(TOP < 16, "a row's entries sit in the first 16 lanes of wave 0");
+  using Sh = Shape<K>;
+  constexpr int W = Sh::W, S = Sh::S, TOP = Sh::TOP, NC = Sh::NC, NT = Sh::NT;
+  constexpr int NTOP = Sh::NTOP, JN = Sh::JN, JT = Sh::JT;
+  static_assert(NC < 65536 && NC * 16 < 65536, "ranks are 16-bit");
+  static_assert(TOP < 16, "a row's entries sit in the first 16 lanes of the wave");
   constexpr int cw = CPLX ? 2 : 1;
   using C = Coef<CPLX>;
-  __shared__ C s_c[2][NC];           // coefficients of the live class, by rank
-  __shared__ uint16_t s_rank[S];     // rank of a mask in its popcount class
-  __shared__ uint16_t s_cls[S];      // masks grouped by popcount, ascending in a group
-  __shared__ C s_a[2][TOP + 1];      // scaled band entries of a row, by row parity
-  __shared__ int s_mx[kWavesPerBlock];  // largest coefficient exponent per wave
+  __shared__ C s_c[kWavesPerBlock][2][NC];     // per wave: the live class, by rank
+  __shared__ C s_a[kWavesPerBlock][TOP + 1];   // per wave: scaled band entries of the row
+  __shared__ uint16_t s_rank[S];               // rank of a mask in its popcount class
+  __shared__ uint16_t s_cls[S];                // masks grouped by popcount, ascending
+  __shared__ int cstart[W + 2];                // first index of each class in s_cls
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
-  const int wave = tid / kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
   typedef const __attribute__((address_space(4))) int32_t* ci32;
   typedef const __attribute__((address_space(4))) int64_t* ci64;
 
-  __shared__ int cstart[W + 2];      // first index of each popcount class in s_cls
   if (tid < W + 2) {
     int v = 0;
     for (int p = 0; p < tid; ++p) v += binom_c(W, p);
@@ -193,36 +215,43 @@ __global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
     s_cls[cstart[j] + r] = (uint16_t)M;
   }
   __syncthreads();
-  // interior sources: rank | column << 16
-  uint32_t src_nt[K + 1];
-  uint32_t src_top = 0;
-  {
-    const int M = tid < NT ? s_cls[cstart[K + 1] + tid] : 0;
+  // interior sources of the lane's masks: rank | column << 16
+  uint32_t src_nt[JN][K + 1];
+  uint32_t src_top[JT];
+#pragma unroll
+  for (int jj = 0; jj < JN; ++jj) {
+    const int r = lane + kWave * jj;
+    const int M = r < NT ? s_cls[cstart[K + 1] + r] : 0;
     const int Q = (M << 1) | 1;
     int q = Q & ~1;
 #pragma unroll
     for (int t = 0; t <= K; ++t) {  // the t-th set column of Q above bit 0
       const int c = q ? __ffs(q) - 1 : 0;
-      src_nt[t] = q ? (s_rank[Q ^ (1 << c)] | ((uint32_t)c << 16)) : 0u;
+      src_nt[jj][t] = q ? (s_rank[Q ^ (1 << c)] | ((uint32_t)c << 16)) : 0u;
       q &= q - 1;
     }
   }
-  if (tid < NTOP) {
-    const int M = s_cls[cstart[K + 1] + NT + tid];
+#pragma unroll
+  for (int jj = 0; jj < JT; ++jj) {
+    const int r = lane + kWave * jj;
+    const int M = r < NTOP ? s_cls[cstart[K + 1] + NT + r] : 0;
     const int Q = (M << 1) | 1;
-    src_top = s_rank[Q ^ (1 << TOP)];
+    src_top[jj] = r < NTOP ? s_rank[Q ^ (1 << TOP)] : 0u;
   }
 
-  for (int m = blockIdx.x; m < a.count; m += gridDim.x) {
+  C (*sc)[NC] = s_c[wave];  // this wave's pair of coefficient buffers
+  C* sa = s_a[wave];
+  for (int m = blockIdx.x * kWavesPerBlock + wave; m < a.count;
+       m += gridDim.x * kWavesPerBlock) {
     const int n = ((ci32)a.n)[m];  // uniform: scalar loads
     const double* A = a.A + ((ci64)a.off)[m];
-    if (tid == 0) {  // p = 0 class: the empty monomial, coefficient 1
-      s_c[0][0].re = 1.0;
-      if constexpr (CPLX) s_c[0][0].im = 0.0;
+    if (lane == 0) {  // p = 0 class: the empty monomial, coefficient 1
+      sc[0][0].re = 1.0;
+      if constexpr (CPLX) sc[0][0].im = 0.0;
     }
-    int esum = 0;
+    int esum = 0, epub = 0;
     bool bad = false;
-    // Lane c of wave 0 holds the entry of column i-k-1+c (c = 1..2k+1) of row i.
+    // Lane c holds the entry of column i-k-1+c (c = 1..2k+1) of row i.
     double vr = 0.0, vi = 0.0;
     auto load_entry = [&](int i) {
       const int j = i - K - 1 + lane;
@@ -234,60 +263,51 @@ __global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
         if constexpr (CPLX) vi = p[1];
       }
     };
-    if (wave == 0) load_entry(0);
-    // Start of row i: wave 0 scales the row's entries into slot i mod 2 and
-    // loads row i+1's; the barrier; then the class exponent published by row
-    // i-1 (on renormalisation rows), uniform.
+    load_entry(0);
+    // Start of row i: the row's entries, scaled, into the wave's slot; row
+    // i+1's loads issued; then the class exponent published by row i-1 (on
+    // renormalisation rows).
     auto head = [&](int i) -> int {
-      if (wave == 0) {
-        const bool nf = !isfinite(vr) || !isfinite(vi);
-        bad = bad || __ballot(nf) != 0;
-        // the exponent of the row's largest entry, from lanes 0..15
-        const int emx = __builtin_amdgcn_readfirstlane(
-            row16_max(max(exponent(vr), exponent(vi))));
-        const int e = (emx != kNoExp && !bad) ? emx : 0;  // scale the row by 2^-e
-        esum += e;
-        if (lane <= TOP) {
-          s_a[i & 1][lane].re = ldexp(vr, -e);
-          if constexpr (CPLX) s_a[i & 1][lane].im = ldexp(vi, -e);
-        }
-        if (i + 1 < n) load_entry(i + 1);  // in flight during row i
+      const bool nf = !isfinite(vr) || !isfinite(vi);
+      bad = bad || __ballot(nf) != 0;
+      // the exponent of the row's largest entry, from lanes 0..15
+      const int emx = __builtin_amdgcn_readfirstlane(
+          row16_max(max(exponent(vr), exponent(vi))));
+      const int e = (emx != kNoExp && !bad) ? emx : 0;  // scale the row by 2^-e
+      esum += e;
+      if (lane <= TOP) {
+        sa[lane].re = ldexp(vr, -e);
+        if constexpr (CPLX) sa[lane].im = ldexp(vi, -e);
       }
-      // one barrier: row i's entries, and row i-1's coefficients, are in LDS
-      __syncthreads();
+      if (i + 1 < n) load_entry(i + 1);  // in flight during row i
+      wave_lds_order();
       int ex = 0;
       if (i > 0 && (i & 3) == 0) {
-        int Mx = s_mx[0];
-#pragma unroll
-        for (int w = 1; w < kWavesPerBlock; ++w) Mx = max(Mx, s_mx[w]);
-        ex = Mx != kNoExp ? Mx : 0;
+        ex = epub != kNoExp ? epub : 0;
         esum += ex;
       }
-      return __builtin_amdgcn_readfirstlane(ex);
+      return ex;
     };
-    // End of row i: every 4 rows, publish the class's largest exponent for row i+1.
+    // End of row i: every 4 rows, the class's largest exponent for row i+1.
     auto tail = [&](int i, int lm) {
-      if ((i & 3) == 3) {
-        lm = wave_max_int(lm);
-        if (lane == 0) s_mx[wave] = lm;
-      }
+      if ((i & 3) == 3) epub = wave_max_int(lm);
+      wave_lds_order();
     };
     // rows 0..k: class i+1 over b0 = 0, sources in class i (ranks from the table)
     const int ng = n < K + 1 ? n : K + 1;
     for (int i = 0; i < ng; ++i) {
       const int ex = head(i);
-      const C* old = s_c[i & 1];
-      C* nw = s_c[(i & 1) ^ 1];
-      const C* ar = s_a[i & 1];
+      const C* old = sc[i & 1];
+      C* nw = sc[(i & 1) ^ 1];
       int lm = kNoExp;
       const int c0 = cstart[i + 1], c1 = cstart[i + 2];
-      for (int r = c0 + tid; r < c1; r += kBlock) {
+      for (int r = c0 + lane; r < c1; r += kWave) {
         const int Q = s_cls[r] << 1;
         double xr_acc = 0.0, xi_acc = 0.0;
         for (int q = (Q >> TOP) & 1 ? (1 << TOP) : Q; q; q &= q - 1) {
           const int c = __ffs(q) - 1;
           const C x = old[s_rank[Q ^ (1 << c)]];
-          const C av = ar[c];
+          const C av = sa[c];
           xr_acc = fma(x.re, av.re, xr_acc);
           if constexpr (CPLX) {
             xr_acc = fma(-x.im, av.im, xr_acc);
@@ -310,42 +330,35 @@ __global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
     int i = K + 1;
     for (; i + 1 < n; i += 2) {
       int ex = head(i);
-      tail(i, interior_row<K, CPLX, P0>(s_c, s_a, src_nt, src_top, tid, ex, (i & 3) == 3));
+      tail(i, interior_row<K, CPLX, P0>(sc, sa, src_nt, src_top, lane, ex, (i & 3) == 3));
       ex = head(i + 1);
-      tail(i + 1, interior_row<K, CPLX, P0 ^ 1>(s_c, s_a, src_nt, src_top, tid, ex,
+      tail(i + 1, interior_row<K, CPLX, P0 ^ 1>(sc, sa, src_nt, src_top, lane, ex,
                                                  ((i + 1) & 3) == 3));
     }
     if (i < n) {
       const int ex = head(i);
-      tail(i, interior_row<K, CPLX, P0>(s_c, s_a, src_nt, src_top, tid, ex, (i & 3) == 3));
+      tail(i, interior_row<K, CPLX, P0>(sc, sa, src_nt, src_top, lane, ex, (i & 3) == 3));
     }
-    const int cur = n & 1;  // the buffer row n-1 wrote
-    __syncthreads();
     // set every remaining x_j = 1: the sum of the class's coefficients, fixed order
+    const C* fin = sc[n & 1];  // the buffer row n-1 wrote
     const int pl = n < K + 1 ? n : K + 1;
     const int cnt = cstart[pl + 1] - cstart[pl];
     dd r{0.0, 0.0}, q{0.0, 0.0};
-    for (int t = tid; t < cnt; t += kBlock) {
-      dd_acc(r, s_c[cur][t].re);
-      if constexpr (CPLX) dd_acc(q, s_c[cur][t].im);
+    for (int t = lane; t < cnt; t += kWave) {
+      dd_acc(r, fin[t].re);
+      if constexpr (CPLX) dd_acc(q, fin[t].im);
     }
     r = wave_sum(r);
     if constexpr (CPLX) q = wave_sum(q);
-    const dd R = block_sum(r, dd_add);
-    dd I{0.0, 0.0};
-    if constexpr (CPLX) {
-      __syncthreads();  // the two sums share block_sum's slots
-      I = block_sum(q, dd_add);
-    }
-    if (tid == 0) {
+    if (lane == 0) {
       double* o = a.out + 4 * (size_t)m;
-      o[0] = bad ? 0.0 : ldexp(R.hi, esum);
-      o[1] = bad ? 0.0 : ldexp(R.lo, esum);
-      o[2] = bad ? 0.0 : ldexp(I.hi, esum);
-      o[3] = bad ? 0.0 : ldexp(I.lo, esum);
+      o[0] = bad ? 0.0 : ldexp(r.hi, esum);
+      o[1] = bad ? 0.0 : ldexp(r.lo, esum);
+      o[2] = bad ? 0.0 : (CPLX ? ldexp(q.hi, esum) : 0.0);
+      o[3] = bad ? 0.0 : (CPLX ? ldexp(q.lo, esum) : 0.0);
       if (a.status) a.status[m] = bad ? kStNonFinite : kStOk;
     }
-    __syncthreads();
+    wave_lds_order();
   }
 }
 

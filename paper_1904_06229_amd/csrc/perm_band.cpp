@@ -140,7 +140,8 @@ extern "C" perm_status perm_band(int dtype, const double* dA, const int32_t* h_n
   int& per_cu = ws->blocks_per_cu[dtype == PERM_DT_COMPLEX ? 1 : 0][k];
   if (per_cu == 0) per_cu = band_blocks_per_cu(dtype == PERM_DT_COMPLEX, k);
   int grid = o.blocks > 0 ? o.blocks : per_cu * ws->cu_count;
-  if (grid > count) grid = count;
+  const int need = (int)((count + kWavesPerBlock - 1) / kWavesPerBlock);  // a wave per matrix
+  if (grid > need) grid = need;
   e = launch_band(dtype == PERM_DT_COMPLEX, k, a, grid, s);
   if (e != hipSuccess) return hip_fail("band launch", e);
   e = hipStreamSynchronize(s);
