@@ -390,13 +390,10 @@ def bench_band(args):
     import numpy as np
     import torch
     from paper_1904_06229_amd import binding as B
+    from paper_1904_06229_amd import inputs
 
     n, k, count, seed = 64, 5, args.count if args.count != 100000 else 20000, 20190407
-    r = np.random.default_rng(seed)
-    i = np.arange(n)
-    mask = np.abs(i[:, None] - i[None, :]) <= k
-    mats = np.where(mask, r.standard_normal((count, n, n)) + 1j * r.standard_normal((count, n, n)),
-                    0) / math.sqrt(2.0)
+    mats = inputs.band_batch(count, n, k, seed)
     flat = np.ascontiguousarray(np.transpose(mats, (0, 2, 1))).ravel().view(np.float64)
     dA = torch.from_numpy(flat).to("cuda")
     sizes = np.full(count, n, dtype=np.int32)

@@ -136,6 +136,17 @@ def ensemble_batch(kind: str, n: int, count: int, seed: int, a: float = 2.0, qr=
     raise ValueError(f"unknown ensemble {kind!r}; one of {ENSEMBLES}")
 
 
+def band_batch(count: int, n: int, k: int, seed: int) -> np.ndarray:
+    """``count`` complex n x n band matrices, a_ij = 0 for |i - j| > k, with
+    Ginibre entries (g1 + i g2)/sqrt(2) on the band (App. C workloads), as a
+    (count, n, n) array."""
+    r = rng(seed)
+    i = np.arange(n)
+    mask = np.abs(i[:, None] - i[None, :]) <= k
+    g = r.standard_normal((count, n, n)) + 1j * r.standard_normal((count, n, n))
+    return np.where(mask, g, 0) / np.sqrt(2.0)
+
+
 # ---- structured matrices with closed-form permanents -----------------------
 
 def ones(n: int) -> np.ndarray:

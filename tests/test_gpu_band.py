@@ -149,3 +149,24 @@ def test_errors(B):
         B.perm_band(dA, [0], [0], 1, False, out)
     with pytest.raises(B.PermError):
         B.perm_band(dA, [4], [0], 1, False, out, log2_chunk=3)
+
+
+def test_bench_sized_batch_sampled(B, orc):
+    """The benchmarked workload at full size: 20000 complex 64 x 64 matrices,
+    k = 5, in the default launch configuration (one wavefront per matrix, grid
+    from the occupancy).  Sampled results against the oracle, every status and
+    value checked, and a 7-workgroup launch (each wave then walks about 700
+    matrices) reproduces every value bit for bit."""
+    from paper_1904_06229_amd import inputs
+    n, k, count, seed = 64, 5, 20000, 20190407
+    mats = inputs.band_batch(count, n, k, seed)
+    log(f"band batch: {count} x {n}x{n}, k = {k}, seed {seed}")
+    vals, st, r = run(B, mats, k, True)
+    assert (st == 0).all() and np.isfinite(r).all()
+    picks = [0, 1, 2, 3, 4, 1023, 9999, 19996, 19997, 19998, 19999]
+    picks += list(np.random.default_rng(7).choice(count, 13, replace=False))
+    for m in picks:
+        want, tol = want_and_tol(orc, mats[m], k)
+        assert abs(vals[m] - want) <= tol, (m, vals[m], want, tol)
+    r7 = run(B, mats, k, True, blocks=7)[2]
+    assert np.array_equal(r, r7)
