@@ -59,6 +59,7 @@ KERNEL_SOURCES = {
     "int01": ["kern_int01.hip", "perm_exact.hpp"],
     "real": ["kern_real.hip", "perm_walk.hpp"],
     "complex": ["kern_complex.hip", "perm_walk.hpp"],
+    "band": ["kern_band.hip"],
 }
 
 
@@ -72,8 +73,8 @@ def _strip_comments(src: str) -> str:
 
 
 def source_sha(kind):
-    """Hash of the code (comments excluded) that a walk kernel is built from:
-    a counter summary stays valid across comment edits, not code edits."""
+    """Hash of the code (comments excluded) that a kernel is built from: a
+    counter summary stays valid across comment edits, not code edits."""
     import hashlib
     base = os.path.join(ROOT, "paper_1904_06229_amd", "csrc")
     h = hashlib.sha256()
@@ -81,6 +82,13 @@ def source_sha(kind):
         with open(os.path.join(base, f), encoding="utf-8") as fh:
             h.update(_strip_comments(fh.read()).encode())
     return h.hexdigest()[:16]
+
+
+def parse_traffic_line(line):
+    """The key=value fields of a TRAFFIC line; a kernel name may hold spaces
+    ("band_kernel<5, true>")."""
+    import re
+    return dict(re.findall(r"(\w+)=(.*?)(?=\s+\w+=|\s*$)", line[len("TRAFFIC "):]))
 
 
 def profiled_traffic(kernel, kind):
@@ -96,10 +104,23 @@ def profiled_traffic(kernel, kind):
             for line in fh:
                 if not line.startswith("TRAFFIC "):
                     continue
-                kv = dict(x.split("=", 1) for x in line.split()[1:])
+                kv = parse_traffic_line(line)
                 if kv.get("kernel") == kernel and kv.get("src") == want:
                     return int(kv["fetch_bytes"]) + int(kv["write_bytes"])
     return None
+
+
+def calibrate_copy():
+    """Two plain 256 MiB device copies, whose FETCH_SIZE and WRITE_SIZE under
+    rocprofv3 give the scale of those counters for the kernels measured in
+    the same run."""
+    import torch
+    src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")  # 256 MiB
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def parse():
@@ -393,6 +414,8 @@ def bench_band(args):
     from paper_1904_06229_amd import inputs
 
     n, k, count, seed = 64, 5, args.count if args.count != 100000 else 20000, 20190407
+    if args.calibrate_copy:
+        calibrate_copy()
     mats = inputs.band_batch(count, n, k, seed)
     flat = np.ascontiguousarray(np.transpose(mats, (0, 2, 1))).ravel().view(np.float64)
     dA = torch.from_numpy(flat).to("cuda")
@@ -428,7 +451,8 @@ def bench_band(args):
                                f"the band, seed {seed}", "n": n, "k": k, "count": count},
         "roofline": {"bound": "lds", "achieved": lds_bytes / (kavg * 1e-3) / 1e9,
                      "peak": PEAK_LDS_BYTES / 1e9, "unit": "GB/s",
-                     "frac": lds_bytes / (kavg * 1e-3) / PEAK_LDS_BYTES, "traffic": None,
+                     "frac": lds_bytes / (kavg * 1e-3) / PEAK_LDS_BYTES,
+                     "traffic": profiled_traffic("band_kernel<5, true>", "band"),
                      "kernel": "band_kernel<5, true>", "kernel_ms": kavg,
                      "macs_per_launch": macs},
         "result_first": repr(complex(res[0] + res[1], res[2] + res[3])),
@@ -683,12 +707,7 @@ def main():
     from paper_1904_06229_amd import binding as B
 
     if args.calibrate_copy:
-        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")  # 256 MiB
-        dst = torch.empty_like(src)
-        for _ in range(2):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        calibrate_copy()
     kind, n, A, desc = make_workload(args.workload)
     dA = torch.from_numpy(np.ascontiguousarray(A)).to("cuda")
     fn = {"int01": B.perm_int01, "real": B.perm_real, "complex": B.perm_complex}[kind]

@@ -38,3 +38,22 @@ def test_defaults(monkeypatch):
 def test_rejected(argv, monkeypatch):
     with pytest.raises(SystemExit):
         parse(argv, monkeypatch)
+
+
+def test_traffic_lines_parse():
+    """Every TRAFFIC line of the committed counter summaries names a kernel, a
+    source hash and two byte counts; kernel names may hold spaces."""
+    import re
+    pdir = os.path.join(ROOT, "profiles")
+    seen = 0
+    for fn in sorted(os.listdir(pdir)):
+        with open(os.path.join(pdir, fn)) as fh:
+            for line in fh:
+                if not line.startswith("TRAFFIC "):
+                    continue
+                kv = bench.parse_traffic_line(line)
+                assert set(kv) == {"kernel", "src", "fetch_bytes", "write_bytes"}, (fn, kv)
+                assert int(kv["fetch_bytes"]) > 0 and int(kv["write_bytes"]) > 0
+                assert re.fullmatch(r"[0-9a-f]{16}", kv["src"])
+                seen += 1
+    assert seen >= 4
