@@ -60,6 +60,8 @@ KERNEL_SOURCES = {
     "real": ["kern_real.hip", "perm_walk.hpp"],
     "complex": ["kern_complex.hip", "perm_walk.hpp"],
     "band": ["kern_band.hip"],
+    "mixed": ["kern_mixed.hip", "perm_exact.hpp", "perm_cases_lo.inc", "perm_cases_hi.inc"],
+    "batched": ["kern_batched.hip", "perm_walk.hpp"],
 }
 
 
@@ -335,6 +337,8 @@ def bench_repeated(args):
     from paper_1904_06229_amd import binding as B, inputs
 
     n, R, seed = 48, 24, 20190406
+    if args.calibrate_copy:
+        calibrate_copy()
     U = inputs.haar_block(n, n * n, seed)
     C = np.ascontiguousarray(U[:, :R])
     mult = [2] * R
@@ -364,7 +368,8 @@ def bench_repeated(args):
                    "n": n, "R": R, "terms": T, "inner_digits": r.log2_chunk, "blocks": r.blocks},
         "roofline": {"bound": "alu", "achieved": alg / (kavg * 1e-3) / 1e12,
                      "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
-                     "frac": alg / (kavg * 1e-3) / PEAK_LANE_OPS, "traffic": None,
+                     "frac": alg / (kavg * 1e-3) / PEAK_LANE_OPS,
+                     "traffic": profiled_traffic(f"mix_walk_kernel<{n}, false> (complex)", "mixed"),
                      "kernel": f"mix_walk_kernel<{n}, false> (complex)", "kernel_ms": kavg,
                      "ops_per_launch": alg},
         "result": repr(complex(r.re_hi + r.re_lo, r.im_hi + r.im_lo)),
@@ -481,6 +486,8 @@ def bench_sparse(args):
     from paper_1904_06229_amd import binding as B
 
     n, p, seed, trials = 64, 0.02, 20190408, 64
+    if args.calibrate_copy:
+        calibrate_copy()
     r = np.random.default_rng(seed)
     M = r.random((n, n)) < p
     np.fill_diagonal(M, True)
@@ -510,7 +517,8 @@ def bench_sparse(args):
                    "log2_sets": math.log2(T), "inner_digits": res.log2_chunk},
         "roofline": {"bound": "alu", "achieved": alg / (kavg * 1e-3) / 1e12,
                      "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
-                     "frac": alg / (kavg * 1e-3) / PEAK_LANE_OPS, "traffic": None,
+                     "frac": alg / (kavg * 1e-3) / PEAK_LANE_OPS,
+                     "traffic": profiled_traffic(f"mix_exact_kernel<{n}, false>", "mixed"),
                      "kernel": f"mix_exact_kernel<{n}, false>", "kernel_ms": kavg,
                      "ops_per_launch": alg,
                      "note": "algorithmic count of the FP64 walk (2n per set); the exact "
@@ -548,6 +556,8 @@ def bench_ensemble(args):
 
     n, seed = 20, 20190405
     count = args.count
+    if args.calibrate_copy:
+        calibrate_copy()
     mats = inputs.ensemble_batch("gaussian", n, count, seed)
     cm = np.ascontiguousarray(np.transpose(mats, (0, 2, 1))).astype(np.complex128)
     dA = torch.from_numpy(cm.ravel().view(np.float64)).to("cuda")
@@ -595,7 +605,9 @@ def bench_ensemble(args):
                    "autotune_s": round(tune_s, 2)},
         "roofline": {"bound": "alu", "achieved": ops / (kavg * 1e-3) / 1e12,
                      "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
-                     "frac": ops / (kavg * 1e-3) / PEAK_LANE_OPS, "traffic": None,
+                     "frac": ops / (kavg * 1e-3) / PEAK_LANE_OPS,
+                     "traffic": (profiled_traffic(f"batched graph, {count} x {n}x{n} complex",
+                                                  "batched")),
                      "kernel": "batched stage+walk+finish (graph)", "kernel_ms": kavg},
         "moments_X": mom, "F_at_1": float(F[np.argmin(np.abs(xg - 1.0))]),
     }
