@@ -5,10 +5,9 @@
 //   walk     one persistent launch per matrix size (largest first): the
 //            items of one size are contiguous in the item array and cost the
 //            same, so wave w takes items w, w + W, w + 2W, ... (W waves in the
-//            grid, numbered XCD by XCD) with no queue; each item's 64 lane
-//            chunks are walked with the same chunk walk as the single-matrix
-//            kernels, fully inlined for that size, and the wave's sum goes
-//            into the item's slot
+//            grid) with no queue; each item's 64 lane chunks are walked with
+//            the same chunk walk as the single-matrix kernels, fully inlined
+//            for that size, and the wave's sum goes into the item's slot
 //   finish   one thread per matrix adds its items' slots in item order
 //            (fixed order, so results are reproducible) and scales by
 //            2(-1)^n and the row-scaling factor
@@ -90,28 +89,12 @@ constexpr int batched_min_waves() {
   return N <= 24 ? 4 : 1;
 }
 
-// Index of the calling wave with the waves numbered XCD by XCD.  Workgroups
-// are dealt to the chip's 8 XCDs round-robin (workgroup g runs on XCD g mod 8),
-// so numbering the waves of workgroups x, x+8, x+16, ... consecutively keeps
-// the consecutive items of one matrix on one XCD, whose L2 then fetches the
-// matrix's staged columns once.  Any grid that is not a multiple of 8 keeps
-// the plain numbering.  Either way every wave index in [0, waves) is used once.
-constexpr uint32_t kXcds = 8;
-__device__ __forceinline__ uint64_t xcd_major_wave_id() {
-  const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const uint32_t g = gridDim.x;
-  if (g % kXcds != 0) return (uint64_t)blockIdx.x * kWavesPerBlock + w;
-  const uint32_t per = g / kXcds;  // workgroups per XCD
-  const uint32_t x = blockIdx.x % kXcds, l = blockIdx.x / kXcds;
-  return ((uint64_t)x * per + l) * kWavesPerBlock + w;
-}
-
 // The items [item0, item0 + nitems), all of size N.
 template <int N, int MODE, bool CPLX>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(batched_min_waves<N>())))
 void batched_size_kernel(BatchArgs a, uint64_t item0, uint64_t nitems) {
   const int lane = threadIdx.x & (kWave - 1);
-  const uint64_t wave = xcd_major_wave_id();
+  const uint64_t wave = wave_id();
   const uint64_t nwaves = (uint64_t)gridDim.x * kWavesPerBlock;
   for (uint64_t q = wave; q < nitems; q += nwaves) {
     const uint64_t idx = item0 + q;
