@@ -1,5 +1,5 @@
 // C-ABI entry point perm_band: permanents of band matrices by the transfer
-// matrix of App. C, one workgroup per matrix.  The sizes and offsets are
+// matrix of App. C, one wavefront per matrix.  The sizes and offsets are
 // copied to a library-owned device array through pinned memory; the call
 // waits for its stream before returning, so the caller's host arrays and the
 // staging memory are free again on return.

@@ -219,7 +219,7 @@ hipError_t launch_sparse_partition(int in_kind, const void* A, int n, int ld, in
                                    uint64_t seed, SparsePart* out, hipStream_t s);
 
 // ------------------------------------------------------------------ band ----
-// App. C transfer matrix (perm_band): one workgroup per matrix.
+// App. C transfer matrix (perm_band): one wavefront per matrix, four per workgroup.
 constexpr int kBandMaxK = 5;  // rank tables of 2^(2k+1) masks in LDS
 
 struct BandArgs {
