@@ -21,15 +21,19 @@ namespace {
 
 __device__ __forceinline__ bool finite(double x) { return isfinite(x); }
 
-// The matrix is first copied into LDS with coalesced loads (all threads), so
-// the per-row statistics read LDS instead of walking a row of global memory
-// one dependent load at a time.
+// Doubles of the matrix each thread copies into LDS (complex n = 64 at most).
+constexpr int kStageLoads = (2 * kMaxN * kMaxN + kBlock - 1) / kBlock;
+
+// The matrix is first copied into LDS (all threads; every load of a thread is
+// issued before the first one is used), so the per-row statistics read LDS
+// instead of walking a row of global memory one dependent load at a time.
 __global__ __launch_bounds__(kBlock) void stage_float_kernel(const double* __restrict__ A, int n,
                                                              int ld, int is_complex,
                                                              int row_scaling, double* staged,
                                                              double* rowabs, int32_t* rowexp,
                                                              int32_t* status) {
   __shared__ double s_a[2 * kMaxN * kMaxN];  // column-major, ld = n (complex: pairs)
+  __shared__ double s_abs[kMaxN * kMaxN];    // |a_ij| 2^e_i, column-major, ld = n
   __shared__ int32_t s_exp[kMaxN];
   __shared__ int32_t s_bad;
   const int tid = threadIdx.x;
@@ -37,10 +41,20 @@ __global__ __launch_bounds__(kBlock) void stage_float_kernel(const double* __res
   const int cw = is_complex ? 2 : 1;  // doubles per entry
   const int nn = n * n;
   const int tot = cw * nn;
-  for (int t = tid; t < tot; t += kBlock) {
-    const int idx = t / cw, c = t - cw * (t / cw);
-    const int i = idx % n, j = idx / n;
-    s_a[t] = A[cw * ((size_t)i + (size_t)j * ld) + c];
+  {
+    double v[kStageLoads];
+#pragma unroll
+    for (int u = 0; u < kStageLoads; ++u) {
+      const int t = tid + u * kBlock;
+      const int idx = t / cw, c = t - cw * (t / cw);
+      const int i = idx % n, j = idx / n;
+      v[u] = t < tot ? A[cw * ((size_t)i + (size_t)j * ld) + c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kStageLoads; ++u) {
+      const int t = tid + u * kBlock;
+      if (t < tot) s_a[t] = v[u];
+    }
   }
   __syncthreads();
   if (tid < n) {
@@ -78,14 +92,18 @@ __global__ __launch_bounds__(kBlock) void stage_float_kernel(const double* __res
     staged[t] = v;
     staged[tot + t] = -v;
   }
+  // |a_ij| 2^e_i by all threads, then each row's sum in column order
+  for (int idx = tid; idx < nn; idx += kBlock) {
+    const int e = s_exp[idx % n];
+    const int o = cw * idx;
+    s_abs[idx] = is_complex ? hypot(ldexp(s_a[o], e), ldexp(s_a[o + 1], e))
+                            : fabs(ldexp(s_a[o], e));
+  }
+  __syncthreads();
   if (tid < n) {
     const int i = tid;
-    const int e = s_exp[i];
     double s = 0.0;
-    for (int j = 0; j < n; ++j) {
-      const int o = cw * (i + j * n);
-      s += is_complex ? hypot(ldexp(s_a[o], e), ldexp(s_a[o + 1], e)) : fabs(ldexp(s_a[o], e));
-    }
+    for (int j = 0; j < n; ++j) s += s_abs[i + j * n];
     rowabs[i] = 0.5 * s;
   }
   if (tid == 0) status[0] = s_bad ? kStNonFinite : kStOk;
@@ -111,16 +129,34 @@ __global__ __launch_bounds__(kBlock) void stage_int01_kernel(const uint8_t* __re
   __shared__ uint8_t s_a[kMaxN * kMaxN];  // s_a[i * kMaxN + j] = a_ij
   __shared__ int32_t s_row[kMaxN], s_col[kMaxN], s_deg[kMaxN], s_csum[kMaxN];
   __shared__ double s_term[kMaxN];
+  __shared__ double s_lg[kMaxN + 1];      // log2(k)
   __shared__ int32_t s_bad;
   const int tid = threadIdx.x;
   if (tid == 0) s_bad = 0;
+  if (tid >= 2 && tid <= kMaxN) s_lg[tid] = log2((double)tid);
   __syncthreads();
   const int nn = n * n;
-  for (int idx = tid; idx < nn; idx += kBlock) {
-    const int i = idx % n, j = idx / n;
-    const uint8_t v = A[(size_t)i + (size_t)j * ld];
-    if (v > 1) atomicOr(&s_bad, 1);
-    s_a[i * kMaxN + j] = v;
+  {
+    // thread t copies rows t mod 64 of the columns t/64, t/64 + 4, ...: every
+    // load of a thread is issued before the first one is used
+    constexpr int kCols = kMaxN / (kBlock / kMaxN);  // columns per thread
+    const int i = tid % kMaxN, j0 = tid / kMaxN;
+    uint8_t v[kCols];
+#pragma unroll
+    for (int u = 0; u < kCols; ++u) {
+      const int j = j0 + u * (kBlock / kMaxN);
+      v[u] = (i < n && j < n) ? A[(size_t)i + (size_t)j * ld] : 0;
+    }
+    int bad = 0;
+#pragma unroll
+    for (int u = 0; u < kCols; ++u) {
+      const int j = j0 + u * (kBlock / kMaxN);
+      if (i < n && j < n) {
+        bad |= v[u] > 1;
+        s_a[i * kMaxN + j] = v[u];
+      }
+    }
+    if (bad) atomicOr(&s_bad, 1);
   }
   __syncthreads();
   // row sums and Bregman terms (threads 0..n-1), column sums (threads 64..64+n-1)
@@ -129,7 +165,7 @@ __global__ __launch_bounds__(kBlock) void stage_int01_kernel(const uint8_t* __re
     for (int j = 0; j < n; ++j) d += s_a[tid * kMaxN + j];
     s_deg[tid] = d;
     double lf = 0.0;
-    for (int k = 2; k <= d; ++k) lf += log2((double)k);
+    for (int k = 2; k <= d; ++k) lf += s_lg[k];
     s_term[tid] = d > 0 ? lf / d : 0.0;
     s_row[tid] = tid;
     s_col[tid] = tid;
