@@ -193,7 +193,9 @@ def make_workload(name):
 
 
 def cpu_baseline(kind, n, A):
-    """The oracle, as it stands, on a bounded sample of the same workload."""
+    """The oracle, as it stands, on a bounded sample of the same workload.
+    Returns the bench-line record, the sample's size and the oracle's value
+    over it."""
     import oracle
     oracle.build(force=False)
     threads = oracle.default_threads()
@@ -201,7 +203,7 @@ def cpu_baseline(kind, n, A):
         # Ryser over a prefix of the 2^n subsets, sized to ~10-20 s on the host.
         count = 1 << n if n <= 30 else 1 << 30
         t0 = time.perf_counter()
-        oracle.ryser_range(A, 0, count, threads=threads)
+        got = oracle.ryser_range(A, 0, count, threads=threads)
         dt = time.perf_counter() - t0
         frac = count / float(1 << n)
         sample = f"integer Ryser over {count} of the 2^{n} subsets ({frac:.3g} of one permanent)"
@@ -212,7 +214,7 @@ def cpu_baseline(kind, n, A):
         count = min(1 << 14, T)
         while True:
             t0 = time.perf_counter()
-            oracle.chunk_partial(A, 0, count, threads=threads)
+            got = oracle.chunk_partial(A, 0, count, threads=threads)
             dt = time.perf_counter() - t0
             if dt >= 5.0 or count >= T:
                 break
@@ -221,8 +223,39 @@ def cpu_baseline(kind, n, A):
         frac = count / float(T)
         sample = f"{count} Gray terms formed directly (long double), {frac:.3g} of one permanent"
     value = frac * n * 2.0 ** (n - 1) / dt
-    return {"value": value, "unit": "n*2^(n-1)/s", "cores": threads, "kind": "oracle",
-            "sample": sample, "seconds": round(dt, 3)}
+    return ({"value": value, "unit": "n*2^(n-1)/s", "cores": threads, "kind": "oracle",
+             "sample": sample, "seconds": round(dt, 3)}, count, got)
+
+
+def oracle_check(kind, n, dA, r, count, want):
+    """The GPU against the oracle's sample of cpu_baseline, outside the timed
+    region.  0/1: the whole permanent when the sample covers all 2^n subsets
+    (Ryser's subset sum is (-1)^n per(A)), compared exactly.  Real and
+    complex: perm_partial over the same Gray prefix [0, count), the relative
+    error of the double-double result against the long-double sum."""
+    from fractions import Fraction
+    from paper_1904_06229_amd import binding as B
+    if kind == "int01":
+        if count != 1 << n:
+            return {"range": f"{count} of the 2^{n} subsets: not a whole permanent",
+                    "checked": False}
+        per = want if n % 2 == 0 else -want
+        return {"range": "whole permanent (all 2^%d subsets)" % n, "checked": True,
+                "exact_match": per == r.exact}
+    dAcm = dA.t().contiguous().t()  # the workload's matrix as a column-major view
+    g = B.perm_partial(dAcm, 0, count)
+    if kind == "complex":
+        wr, wi = want.re.exact, want.im.exact
+        dr = Fraction(g.re_hi) + Fraction(g.re_lo) - wr
+        di = Fraction(g.im_hi) + Fraction(g.im_lo) - wi
+        err = math.sqrt(float(dr * dr + di * di)) / math.sqrt(float(wr * wr + wi * wi))
+    else:
+        w = want.exact
+        err = abs(float(Fraction(g.re_hi) + Fraction(g.re_lo) - w)) / abs(float(w))
+    whole = count == 1 << (n - 1)
+    return {"range": (f"whole half-range sum ({count} Gray terms)" if whole else
+                      f"Gray prefix [0, {count}) of 2^{n - 1}"),
+            "checked": True, "rel_err_vs_oracle": err, "tolerance": 1e-10}
 
 
 def gpu_qr(G):
@@ -693,7 +726,9 @@ def bench_sliced(args):
         "result": res,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(kind, n, A)
+        cb, count, want = cpu_baseline(kind, n, A)
+        out["cpu_baseline"] = cb
+        out["oracle_check"] = oracle_check(kind, n, dA, None, count, want)
     print(json.dumps(out))
 
 
@@ -774,8 +809,9 @@ def main():
     else:
         out["result"] = repr(r.value)
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(kind, n, A)
+        cb, count, want = cpu_baseline(kind, n, A)
         out["cpu_baseline"] = cb
+        out["oracle_check"] = oracle_check(kind, n, dA, r, count, want)
     print(json.dumps(out))
 
 

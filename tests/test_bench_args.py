@@ -57,3 +57,23 @@ def test_traffic_lines_parse():
                 assert re.fullmatch(r"[0-9a-f]{16}", kv["src"])
                 seen += 1
     assert seen >= 4
+
+
+def test_oracle_check_int01_sign_and_coverage():
+    """The 0/1 check turns Ryser's subset sum, (-1)^n per(A), into per(A)
+    before comparing, and refuses a sample that is not the whole permanent.
+    A planted sign error in the comparison would fail one of the two n."""
+    import numpy as np
+    import oracle
+    from types import SimpleNamespace
+    oracle.build(force=False)
+    for n, seed in ((7, 2), (8, 1)):
+        A = (np.random.default_rng(seed).random((n, n)) < 0.6).astype(np.uint8)
+        per = oracle.brute(A)
+        raw = oracle.ryser_range(A, 0, 1 << n)
+        good = bench.oracle_check("int01", n, None, SimpleNamespace(exact=per), 1 << n, raw)
+        assert good["checked"] and good["exact_match"]
+        bad = bench.oracle_check("int01", n, None, SimpleNamespace(exact=per + 1), 1 << n, raw)
+        assert bad["checked"] and not bad["exact_match"]
+        part = bench.oracle_check("int01", n, None, SimpleNamespace(exact=per), 1 << (n - 1), raw)
+        assert not part["checked"]
