@@ -28,6 +28,7 @@ import math
 import os
 import sys
 import time
+from types import SimpleNamespace
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -245,10 +246,7 @@ def oracle_check(kind, n, dA, r, count, want):
     dAcm = dA.t().contiguous().t()  # the workload's matrix as a column-major view
     g = B.perm_partial(dAcm, 0, count)
     if kind == "complex":
-        wr, wi = want.re.exact, want.im.exact
-        dr = Fraction(g.re_hi) + Fraction(g.re_lo) - wr
-        di = Fraction(g.im_hi) + Fraction(g.im_lo) - wi
-        err = math.sqrt(float(dr * dr + di * di)) / math.sqrt(float(wr * wr + wi * wi))
+        err = complex_rel_err(g, want)
     else:
         w = want.exact
         err = abs(float(Fraction(g.re_hi) + Fraction(g.re_lo) - w)) / abs(float(w))
@@ -414,7 +412,7 @@ def bench_repeated(args):
         count = 1 << 12
         while True:
             t1 = time.perf_counter()
-            oracle.ryser2_range(C, mult, 0, count, threads=threads)
+            want = oracle.ryser2_range(C, mult, 0, count, threads=threads)
             cdt = time.perf_counter() - t1
             if cdt >= 5.0 or count >= T:
                 break
@@ -423,7 +421,22 @@ def bench_repeated(args):
                                "cores": threads, "kind": "oracle",
                                "sample": f"first {count} of the {T} Gray terms, each formed "
                                          "directly (long double)", "seconds": round(cdt, 3)}
+        # the same prefix on the GPU (outside the timed region)
+        g = B.perm_repeated_partial(dC, mult, 0, count)
+        out["oracle_check"] = {"range": f"mixed-radix Gray prefix [0, {count}) of {T}",
+                               "checked": True, "tolerance": 1e-10,
+                               "rel_err_vs_oracle": complex_rel_err(g, want)}
     print(json.dumps(out))
+
+
+def complex_rel_err(g, want):
+    """|g - want| / |want| for a library result g and an oracle CPair, in exact
+    rational arithmetic on the double-double parts."""
+    from fractions import Fraction
+    wr, wi = want.re.exact, want.im.exact
+    dr = Fraction(g.re_hi) + Fraction(g.re_lo) - wr
+    di = Fraction(g.im_hi) + Fraction(g.im_lo) - wi
+    return math.sqrt(float(dr * dr + di * di)) / math.sqrt(float(wr * wr + wi * wi))
 
 
 # LDS: 128 bytes per clock per CU (gfx950), 256 CUs, 2.4 GHz.
@@ -499,11 +512,18 @@ def bench_band(args):
         import oracle
         oracle.build(force=False)
         t1 = time.perf_counter()
-        done = 0
+        done, wants = 0, []
         while time.perf_counter() - t1 < 10.0 and done < count:
-            oracle.band(mats[done], k)
+            wants.append(oracle.band(mats[done], k))
             done += 1
         cdt = time.perf_counter() - t1
+        got = out.view(-1, 4)[:done].cpu().numpy()
+        worst = max(complex_rel_err(SimpleNamespace(re_hi=g[0], re_lo=g[1], im_hi=g[2],
+                                                    im_lo=g[3]), w)
+                    for g, w in zip(got, wants))
+        o["oracle_check"] = {"range": f"the first {done} matrices of the batch",
+                             "checked": True, "tolerance": 1e-10,
+                             "max_rel_err_vs_oracle": worst}
         o["cpu_baseline"] = {"value": done / cdt, "unit": "permanents/s", "cores": 1,
                              "kind": "oracle", "sample": f"first {done} matrices of the batch, "
                              "long-double transfer matrix, one thread", "seconds": round(cdt, 2)}
@@ -562,18 +582,24 @@ def bench_sparse(args):
         import oracle
         oracle.build(force=False)
         threads = oracle.default_threads()
-        count = 1 << 12
+        # the oracle's exact integer App. B sum over a prefix of its own enumeration
+        # (one greedy partition trial, as perm_sparse_partial's default)
+        T1 = B.perm_sparse_partition(dA)[2]  # sets of the one-trial enumeration
+        count = min(1 << 12, T1)
         while True:
             t1 = time.perf_counter()
-            oracle.sparse_range(A, 0, count, threads=threads)
+            want = oracle.sparse_range_int(A, 0, count, threads=threads)
             cdt = time.perf_counter() - t1
-            if cdt >= 5.0 or count >= T:
+            if cdt >= 5.0 or count >= T1:
                 break
-            count = min(T, count * 2 ** max(1, min(8, int(math.log2(10.0 / max(cdt, 1e-4))))))
+            count = min(T1, count * 2 ** max(1, min(8, int(math.log2(10.0 / max(cdt, 1e-4))))))
         out["cpu_baseline"] = {"value": n * count / cdt, "unit": "n*sets/s", "cores": threads,
-                               "kind": "oracle", "sample": f"first {count} of the {T} column sets "
-                               "of the Gray enumeration, each term formed directly",
-                               "seconds": round(cdt, 3)}
+                               "kind": "oracle", "sample": f"first {count} column sets of the "
+                               "Gray enumeration (one partition trial), each term formed "
+                               "directly, exact integers", "seconds": round(cdt, 3)}
+        g = B.perm_sparse_partial(dA, 0, count)
+        out["oracle_check"] = {"range": f"Gray prefix [0, {count}) of the one-trial enumeration",
+                               "checked": True, "exact_match": g.exact == want}
     print(json.dumps(out))
 
 
