@@ -230,3 +230,25 @@ def test_zero_row_and_errors(B):
     bad[1, 1] = np.inf
     with pytest.raises(B.PermError):
         B.perm_sparse(dev(bad))
+
+
+def test_bench_workload_two_enumerations_exact(B, orc):
+    """The benchmarked sparse workload at full size: n = 64, p = 0.02, seed
+    20190408, App. B with 64 partition trials (seed 1).  Its exact permanent
+    must equal, bit for bit, the one from the oracle's own partition (one
+    greedy trial: another enumeration of other column sets), and sampled
+    ranges of that enumeration match the oracle's exact integer sums."""
+    A = sparse_matrix(64, 0.02, 20190408, "int")
+    dA = dev(A)
+    blk1, _, T1 = B.perm_sparse_partition(dA)
+    blk64, _, T64 = B.perm_sparse_partition(dA, trials=64, seed=1)
+    log(f"n=64 p=0.02: one trial {T1} sets (2^{math.log2(T1):.1f}), 64 trials {T64} sets "
+        f"(2^{math.log2(T64):.1f}); partitions differ: {list(blk1) != list(blk64)}")
+    assert T64 <= T1
+    a = B.perm_sparse(dA, trials=64, seed=1)
+    assert a.exact > 0
+    if T1 <= 1 << 42:
+        assert B.perm_sparse(dA).exact == a.exact
+    for s, c in ((0, 1 << 16), (T1 - (1 << 12), 1 << 12), (T1 // 3, 4099)):
+        got = B.perm_sparse_partial(dA, s, c)
+        assert got.exact == orc.sparse_range_int(A, s, c), (s, c)
