@@ -151,3 +151,73 @@ def test_argument_errors(B):
     with pytest.raises(B.PermError):
         B.perm_batched(dA, [4], [0], False, out, precision="split")
     B.perm_batched(dA, [], [], False, out)  # empty batch is a no-op
+
+
+def test_haar_batch_full_size_sampled(B, orc, inp):
+    """The benchmarked batch at full size: 100000 complex Haar blocks, n uniform
+    on 8..24 (seed 20190404), in the benchmark's launch configuration (HIP graph
+    replay on a side stream).  Every status and value checked, an eager launch
+    reproduces the graph's values bit for bit, and two matrices of every size
+    against the oracle's Ryser sum."""
+    def gpu_qr(G):  # stacked thin QR on the device (input generation only)
+        Q, R = torch.linalg.qr(torch.from_numpy(G).to("cuda"), mode="reduced")
+        return Q.cpu().numpy(), R.cpu().numpy()
+
+    log("Haar batch: generating 100000 blocks, n 8..24, seed 20190404")
+    sizes, mats = inp.batched_haar_blocks(100000, 8, 24, 20190404, qr=gpu_qr)
+    dA, offs = pack(mats, True)
+    count = len(sizes)
+    out = torch.zeros(4 * count, dtype=torch.float64, device="cuda")
+    st = torch.full((count,), -1, dtype=torch.int32, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        B.perm_batched(dA, sizes, offs, True, out, st, stream=s, use_graph=True)
+        B.perm_batched(dA, sizes, offs, True, out, st, stream=s, use_graph=True)
+        s.synchronize()
+    graph = out.cpu().numpy().reshape(-1, 4)
+    assert (st.cpu().numpy() == 0).all() and np.isfinite(graph).all()
+    out.zero_()
+    B.perm_batched(dA, sizes, offs, True, out, st)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().reshape(-1, 4), graph)
+    log("Haar batch: values checked; oracle on two matrices of every size")
+    first = {}
+    r = np.random.default_rng(3)
+    for k, n in enumerate(sizes):
+        first.setdefault(n, []).append(k)
+    for n in sorted(first):
+        for k in (first[n][0], int(r.choice(first[n]))):
+            w = orc.ryser(mats[k])
+            want = complex(w.re.hi + w.re.lo, w.im.hi + w.im.lo)
+            got = complex(graph[k][0] + graph[k][1], graph[k][2] + graph[k][3])
+            assert rel(got, want) < TOL, (k, n, got, want)
+
+
+def test_ginibre_ensemble_batch_full_size_sampled(B, orc, inp):
+    """The benchmarked ensemble batch at full size: 100000 Ginibre 20 x 20
+    matrices (seed 20190405), graph replay on a side stream.  Twenty sampled
+    values against the oracle, and the sample mean of X^2 = |per|^2 / 20!
+    against its exact expectation 1 (E|per|^2 = n! for iid unit-variance
+    entries; Var X^2 = n for complex Gaussian entries, so the standard error
+    of the mean is sqrt(20 / 100000) = 0.014)."""
+    n, count = 20, 100000
+    mats = inp.ensemble_batch("gaussian", n, count, 20190405)
+    cm = np.ascontiguousarray(np.transpose(mats, (0, 2, 1))).astype(np.complex128)
+    dA = torch.from_numpy(cm.ravel().view(np.float64)).to("cuda")
+    sizes = np.full(count, n, dtype=np.int32)
+    offs = np.arange(count, dtype=np.int64) * (2 * n * n)
+    out = torch.zeros(4 * count, dtype=torch.float64, device="cuda")
+    st = torch.full((count,), -1, dtype=torch.int32, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        B.perm_batched(dA, sizes, offs, True, out, st, stream=s, use_graph=True)
+        s.synchronize()
+    o = out.cpu().numpy().reshape(-1, 4)
+    assert (st.cpu().numpy() == 0).all() and np.isfinite(o).all()
+    per = (o[:, 0] + o[:, 1]) + 1j * (o[:, 2] + o[:, 3])
+    for k in np.random.default_rng(4).choice(count, 20, replace=False):
+        w = orc.ryser(mats[k])
+        assert rel(per[k], complex(w.re.hi + w.re.lo, w.im.hi + w.im.lo)) < TOL, k
+    x2 = np.abs(per) ** 2 / math.factorial(n)
+    log(f"Ginibre n=20: mean X^2 = {x2.mean():.4f} over {count}")
+    assert abs(x2.mean() - 1.0) < 5 * math.sqrt(n / count)
