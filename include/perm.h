@@ -84,7 +84,10 @@ typedef struct {
   int32_t log2_chunk;    /* chunk length used */
   int32_t blocks;        /* workgroups of the main walk launch */
   float kernel_ms;       /* duration of the walk launches, from HIP events on `stream` */
-  float total_ms;        /* duration of the whole call on `stream` (staging to result) */
+  float total_ms;        /* perm_real, perm_complex, perm_int01, perm_partial: wall time of
+                            the call on the host, from entry until the result is in host
+                            memory.  perm_repeated*, perm_sparse*: HIP events on `stream`
+                            from staging to the result */
   int32_t walk_variant;  /* perm_int01: 1 if the pair-shared walk ran, else 0.  perm_sparse
                             with PERM_DT_INT01: the row groups of the exact product (1..4),
                             or 0 for the size-only grouping.  Otherwise 0 */
