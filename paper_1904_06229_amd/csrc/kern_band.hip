@@ -30,7 +30,10 @@
 // first in rank order (they are the smaller numbers); lane l owns the masks
 // l, l+64, ... of each kind (k+1 sources for the first kind, one for the
 // second) and keeps their source ranks and columns in registers for the whole
-// launch.  The first k+1 rows, where the class grows, look the ranks up in LDS.
+// launch.  A term whose column is the same in every lane (column i+k, and the
+// high columns of the later colex slots) takes the row's entry from a scalar
+// register instead of LDS.  The first k+1 rows, where the class grows, look
+// the ranks up in LDS.
 //
 // One wavefront per matrix, four per workgroup, each with its own pair of
 // coefficient buffers and its own row slot; the rank tables are shared.  A row
@@ -44,6 +47,9 @@
 // exponents with DPP lane permutes and lane reads, which keeps LDS round trips
 // off the row.  The exponents are restored at the end.  The final coefficient
 // sum is a fixed-order double-double reduction.
+#include <type_traits>
+#include <utility>
+
 #include "perm_device.hpp"
 #include "perm_internal.hpp"
 
@@ -95,6 +101,49 @@ struct Coef<false> {
   double re;
 };
 
+// The mask of colex rank r among the p-subsets of the bits 0, 1, 2, ...: its
+// set bits b_p > ... > b_1 are, in turn, the largest b with binom(b, j) not
+// above what is left of r (the combinatorial number system read backwards).
+__host__ __device__ constexpr int unrank_colex(int r, int p) {
+  int m = 0;
+  for (int j = p; j >= 1; --j) {
+    int b = j - 1;
+    while (binom_c(b + 1, j) <= r) ++b;
+    m |= 1 << b;
+    r -= binom_c(b, j);
+  }
+  return m;
+}
+
+// Position of the t-th lowest set bit of m (t = 0: the lowest), or -1.
+__host__ __device__ constexpr int nth_bit(int m, int t) {
+  for (int b = 0; b < 31; ++b) {
+    if ((m >> b) & 1) {
+      if (t == 0) return b;
+      --t;
+    }
+  }
+  return -1;
+}
+
+// f(integral_constant<int, 0>), ..., f(integral_constant<int, N-1>), in order.
+template <class F, int... J>
+__device__ __forceinline__ void for_each_index_impl(F&& f, std::integer_sequence<int, J...>) {
+  (f(std::integral_constant<int, J>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void for_each_index(F&& f) {
+  for_each_index_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Lane `lane`'s value of a wave-uniform read of v (a scalar register).
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // Sizes of the live class for half-width K.
 template <int K>
 struct Shape {
@@ -107,6 +156,22 @@ struct Shape {
   // of the first kind per lane (at least one slot: k = 0 has none)
   static constexpr int JN = NT > 0 ? (NT + kWave - 1) / kWave : 1;
   static constexpr int JT = (NTOP + kWave - 1) / kWave;  // of the second kind per lane
+  // The column of term t (the t-th set column of Q above bit 0) of every
+  // mask in slot jj of the first kind (ranks 64 jj .. 64 jj + 63), when it is
+  // the same for all of them, else -1.  Ranks are colex, so the high columns
+  // agree within the later slots.  Such a term takes the row's entry from a
+  // scalar register instead of LDS.
+  static constexpr int uniform_col(int jj, int t) {
+    int c = -1;
+    for (int r = kWave * jj; r < NT && r < kWave * (jj + 1); ++r) {
+      const int cr = nth_bit(unrank_colex(r, K + 1), t) + 1;
+      if (c == -1)
+        c = cr;
+      else if (c != cr)
+        return -1;
+    }
+    return c;
+  }
 };
 
 // One interior row (i > k: b0 = 1, class k+1 before and after) for the
@@ -114,9 +179,39 @@ struct Shape {
 // mod 2, fixed at compile time so that every LDS address is a loop-invariant
 // register plus a constant); the results go to buffer P ^ 1, scaled by
 // 2^-ex.  When pub is set, returns the largest exponent written.
+//
+// One term of a first-kind mask of slot JJ: coefficient times row entry, the
+// entry from the scalar copy au when its column is the same in every lane.
+template <int K, bool CPLX, int JJ, int T>
+__device__ __forceinline__ void nt_term(double& xr_acc, double& xi_acc, const Coef<CPLX>* old,
+                                        const Coef<CPLX>* ar, const Coef<CPLX> (&au)[2 * K + 2],
+                                        uint32_t src) {
+  constexpr int cu = Shape<K>::uniform_col(JJ, T);
+  const Coef<CPLX> x = old[src & 0xffff];
+  Coef<CPLX> av;
+  if constexpr (cu >= 0)
+    av = au[cu];
+  else
+    av = ar[src >> 16];
+  xr_acc = fma(x.re, av.re, xr_acc);
+  if constexpr (CPLX) {
+    xr_acc = fma(-x.im, av.im, xr_acc);
+    xi_acc = fma(x.re, av.im, fma(x.im, av.re, xi_acc));
+  }
+}
+
+template <int K, bool CPLX, int JJ, int... T>
+__device__ __forceinline__ void nt_terms(double& xr_acc, double& xi_acc, const Coef<CPLX>* old,
+                                         const Coef<CPLX>* ar, const Coef<CPLX> (&au)[2 * K + 2],
+                                         const uint32_t (&src)[K + 1],
+                                         std::integer_sequence<int, T...>) {
+  (nt_term<K, CPLX, JJ, T>(xr_acc, xi_acc, old, ar, au, src[T]), ...);  // t = 0, 1, ..., K
+}
+
 template <int K, bool CPLX, int P>
 __device__ __forceinline__ int interior_row(Coef<CPLX> (*sc)[Shape<K>::NC],
                                             const Coef<CPLX>* ar,
+                                            const Coef<CPLX> (&au)[2 * K + 2],
                                             const uint32_t (&src_nt)[Shape<K>::JN][K + 1],
                                             const uint32_t (&src_top)[Shape<K>::JT], int lane,
                                             int ex, bool pub) {
@@ -139,25 +234,17 @@ __device__ __forceinline__ int interior_row(Coef<CPLX> (*sc)[Shape<K>::NC],
     }
     nw[r] = v;
   };
-#pragma unroll
-  for (int jj = 0; jj < Sh::JN; ++jj) {
-    const int r = lane + kWave * jj;
+  for_each_index<Sh::JN>([&](auto jjc) {
+    constexpr int JJ = decltype(jjc)::value;
+    const int r = lane + kWave * JJ;
     if (r < Sh::NT) {
       double xr_acc = 0.0, xi_acc = 0.0;
-#pragma unroll
-      for (int t = 0; t <= K; ++t) {
-        const C x = old[src_nt[jj][t] & 0xffff];
-        const C av = ar[src_nt[jj][t] >> 16];
-        xr_acc = fma(x.re, av.re, xr_acc);
-        if constexpr (CPLX) {
-          xr_acc = fma(-x.im, av.im, xr_acc);
-          xi_acc = fma(x.re, av.im, fma(x.im, av.re, xi_acc));
-        }
-      }
+      nt_terms<K, CPLX, JJ>(xr_acc, xi_acc, old, ar, au, src_nt[JJ],
+                            std::make_integer_sequence<int, K + 1>{});
       put(r, xr_acc, xi_acc);
     }
-  }
-  const C at = ar[Sh::TOP];
+  });
+  const C at = au[Sh::TOP];  // column i+k: the same for every mask of the second kind
 #pragma unroll
   for (int jj = 0; jj < Sh::JT; ++jj) {
     const int r = lane + kWave * jj;
@@ -241,6 +328,7 @@ __global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
 
   C (*sc)[NC] = s_c[wave];  // this wave's pair of coefficient buffers
   C* sa = s_a[wave];
+  C au[TOP + 1];            // the row's scaled entries as wave-uniform (scalar) values
   for (int m = blockIdx.x * kWavesPerBlock + wave; m < a.count;
        m += gridDim.x * kWavesPerBlock) {
     const int n = ((ci32)a.n)[m];  // uniform: scalar loads
@@ -275,9 +363,17 @@ __global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
           row16_max(max(exponent(vr), exponent(vi))));
       const int e = (emx != kNoExp && !bad) ? emx : 0;  // scale the row by 2^-e
       esum += e;
+      const double sr = ldexp(vr, -e), si = ldexp(vi, -e);
       if (lane <= TOP) {
-        sa[lane].re = ldexp(vr, -e);
-        if constexpr (CPLX) sa[lane].im = ldexp(vi, -e);
+        sa[lane].re = sr;
+        if constexpr (CPLX) sa[lane].im = si;
+      }
+      // scalar copies (the interior rows use those of the columns that are the
+      // same in every lane; the other reads are dead and dropped)
+#pragma unroll
+      for (int c = 1; c <= TOP; ++c) {
+        au[c].re = readlane_d(sr, c);
+        if constexpr (CPLX) au[c].im = readlane_d(si, c);
       }
       if (i + 1 < n) load_entry(i + 1);  // in flight during row i
       wave_lds_order();
@@ -330,14 +426,14 @@ __global__ __launch_bounds__(kBlock) void band_kernel(BandArgs a) {
     int i = K + 1;
     for (; i + 1 < n; i += 2) {
       int ex = head(i);
-      tail(i, interior_row<K, CPLX, P0>(sc, sa, src_nt, src_top, lane, ex, (i & 3) == 3));
+      tail(i, interior_row<K, CPLX, P0>(sc, sa, au, src_nt, src_top, lane, ex, (i & 3) == 3));
       ex = head(i + 1);
-      tail(i + 1, interior_row<K, CPLX, P0 ^ 1>(sc, sa, src_nt, src_top, lane, ex,
+      tail(i + 1, interior_row<K, CPLX, P0 ^ 1>(sc, sa, au, src_nt, src_top, lane, ex,
                                                  ((i + 1) & 3) == 3));
     }
     if (i < n) {
       const int ex = head(i);
-      tail(i, interior_row<K, CPLX, P0>(sc, sa, src_nt, src_top, lane, ex, (i & 3) == 3));
+      tail(i, interior_row<K, CPLX, P0>(sc, sa, au, src_nt, src_top, lane, ex, (i & 3) == 3));
     }
     // set every remaining x_j = 1: the sum of the class's coefficients, fixed order
     const C* fin = sc[n & 1];  // the buffer row n-1 wrote
