@@ -77,3 +77,17 @@ def test_oracle_check_int01_sign_and_coverage():
         assert bad["checked"] and not bad["exact_match"]
         part = bench.oracle_check("int01", n, None, SimpleNamespace(exact=per), 1 << (n - 1), raw)
         assert not part["checked"]
+
+
+def test_complex_rel_err_formula():
+    """complex_rel_err measures |g - want| / |want| on the double-double parts
+    exactly: a known perturbation of each part gives the known error, and a
+    result equal to the oracle's gives 0."""
+    import math
+    from types import SimpleNamespace
+    from oracle import CPair, Pair
+    want = CPair(Pair(3.0, 2.0 ** -60), Pair(-4.0, 0.0))
+    same = SimpleNamespace(re_hi=3.0, re_lo=2.0 ** -60, im_hi=-4.0, im_lo=0.0)
+    assert bench.complex_rel_err(same, want) == 0.0
+    off = SimpleNamespace(re_hi=3.0, re_lo=2.0 ** -60 + 3e-9, im_hi=-4.0, im_lo=4e-9)
+    assert math.isclose(bench.complex_rel_err(off, want), 5e-9 / 5.0, rel_tol=1e-9)
