@@ -91,3 +91,15 @@ def test_complex_rel_err_formula():
     assert bench.complex_rel_err(same, want) == 0.0
     off = SimpleNamespace(re_hi=3.0, re_lo=2.0 ** -60 + 3e-9, im_hi=-4.0, im_lo=4e-9)
     assert math.isclose(bench.complex_rel_err(off, want), 5e-9 / 5.0, rel_tol=1e-9)
+
+
+def test_more_than_one_gpu_refused(monkeypatch, capsys):
+    """The benchmark measures one GPU: --gpus above 1 ends with a message
+    (and exit status 2) before anything touches a device."""
+    import json
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--gpus", "2"])
+    with pytest.raises(SystemExit) as e:
+        bench.main()
+    assert e.value.code == 2
+    line = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    assert "one GPU" in line["error"]
