@@ -99,7 +99,8 @@ typedef struct {
  * perm_real -- per(A) of a real n x n matrix (FP64 input).
  *   dA      device pointer, column-major, leading dimension ld >= max(n,1).
  *   out     host pointer; value in re_hi + re_lo (relative error of the default
- *           precision: about 1e-15..1e-11 depending on cancellation; see docs).
+ *           precision: about 1e-15..1e-11, depending on the cancellation among the
+ *           terms).
  * Errors: PERM_EINVAL (n < 0, n > 64, ld < n, bad opts), PERM_ENONFINITE, PERM_EHIP.
  */
 perm_status perm_real(const double* dA, int n, int ld, const perm_opts* opts,
