@@ -151,6 +151,20 @@ def test_errors(B):
         B.perm_band(dA, [4], [0], 1, False, out, log2_chunk=3)
 
 
+def test_empty_and_single_matrix_batches(B, orc):
+    """An empty batch is a no-op (the output is untouched); a batch of one
+    matrix leaves three of the workgroup's four waves without work."""
+    dA = torch.zeros(16, dtype=torch.float64, device="cuda")
+    out = torch.full((4,), 7.0, dtype=torch.float64, device="cuda")
+    B.perm_band(dA, [], [], 3, True, out)
+    torch.cuda.synchronize()
+    assert (out.cpu().numpy() == 7.0).all()
+    M = band_matrix(37, 4, 12, True)
+    vals, st, _ = run(B, [M], 4, True)
+    want, tol = want_and_tol(orc, M, 4)
+    assert st[0] == 0 and abs(vals[0] - want) <= tol
+
+
 def test_bench_sized_batch_sampled(B, orc):
     """The benchmarked workload at full size: 20000 complex 64 x 64 matrices,
     k = 5, in the default launch configuration (one wavefront per matrix, grid
