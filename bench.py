@@ -1,24 +1,30 @@
 """Benchmark of the Gray-code permanent on one MI355X.
 
-Default workload: one 30x30 0/1 matrix with iid Bernoulli(1/2) entries (seed
-20190413), exact permanent (2^29 Gray terms).  A step is one full library
-call: staging, the walk over all 2^(n-1) terms, the fixed-order reduction and
-the copy of the result to the host; the matrix is resident in HBM before the
-timed region starts.  The metric counts n * 2^(n-1) element-steps per
-permanent.
+Default workload: the 40 x 40 top-left block of a 1600-mode Haar unitary
+(complex128, seed 20190402), its whole permanent in FP64 with double-double
+sums (2^39 Gray terms).  A step is one full library call: staging, the walk
+over all 2^(n-1) terms, the fixed-order reduction and the result on the host;
+the matrix is resident in HBM before the timed region starts.  The metric
+counts n * 2^(n-1) element-steps per permanent.
 
 Printed: one JSON line with the throughput, the roofline of the walk kernel
 (VALU lane-operations of the algorithm per second against the chip's vector
 issue peak; the kernel's own duration comes from HIP events recorded by the
-library on the launch stream), and the CPU oracle timed on the host cores.
+library on the launch stream), the CPU oracle timed on the host cores, the
+GPU against the oracle's own sample, and -- outside the timed region -- the
+same permanent with plain FP64 sums and with FP32 products (their relative
+difference to the timed result), and the batched distribution study (100000
+Haar blocks, n uniform on 8..24) as permanents/s.
 
-Other workloads (--workload c1|c3|c4|c5|c6|c7|c8|c9) are for manual runs; c5 (48x48
-real, 2^47 terms, minutes per permanent) runs as 16 perm_partial slices with
-a progress line each; c6 is the repeated-column path (Eq. ryser2) on a
-48-photon output with two photons in each of 24 modes; c7 is the band
-transfer matrix (App. C) on a batch of 64 x 64 band matrices; c8 the exact
-sparse path (App. B) on the paper's identity + Bernoulli(p) matrices; c9 the
-random-ensemble study (Sec. III) on 100000 Ginibre 20 x 20 matrices.
+Other workloads (--workload c1|c2|c4|c5|c6|c7|c8|c9) are for manual runs: c1
+the 20 x 20 complex call; c2 the exact 30 x 30 0/1 permanent; c4 the
+batched study alone; c5 (48x48 real, 2^47 terms, minutes per permanent) runs
+as 16 perm_partial slices with a progress line each; c6 is the
+repeated-column path (Eq. ryser2) on a 48-photon output with two photons in
+each of 24 modes; c7 is the band transfer matrix (App. C) on a batch of
+64 x 64 band matrices; c8 the exact sparse path (App. B) on the paper's
+identity + Bernoulli(p) matrices; c9 the random-ensemble study (Sec. III) on
+100000 Ginibre 20 x 20 matrices.
 """
 from __future__ import annotations
 
@@ -135,7 +141,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=None,
                    help="untimed steps first (default 3; c3, c4, c6, c8: 1; 0 for a whole "
                         "sliced permanent)")
-    p.add_argument("--workload", default="c2",
+    p.add_argument("--workload", default="c3",
                    choices=["c1", "c2", "c3", "c4", "c5", "c6", "c7", "c8", "c9"])
     p.add_argument("--count", type=int, default=100000, help="c4: number of matrices")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -150,6 +156,11 @@ def parse():
     p.add_argument("--checkpoint", default=None, help="slice checkpoint file (resume)")
     p.add_argument("--terms-log2", type=int, default=0,
                    help="time only the first 2^K Gray terms (perm_partial); labelled as a prefix")
+    p.add_argument("--no-batched", action="store_true",
+                   help="c3: leave out the batched study that follows the timed region")
+    p.add_argument("--no-compare", action="store_true",
+                   help="c1, c3: leave out the plain-FP64 and FP32-product runs after the timed "
+                        "region")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run a plain 256 MiB device copy (scale reference for HBM counters)")
     args = p.parse_args()
@@ -228,12 +239,16 @@ def cpu_baseline(kind, n, A):
              "sample": sample, "seconds": round(dt, 3)}, count, got)
 
 
-def oracle_check(kind, n, dA, r, count, want):
+DTYPES = {"dd": "f64 (double-double sums)", "fp64": "f64",
+          "split": "f32 products of f64 row sums, double-double sums"}
+
+
+def oracle_check(kind, n, dA, r, count, want, precision="dd"):
     """The GPU against the oracle's sample of cpu_baseline, outside the timed
     region.  0/1: the whole permanent when the sample covers all 2^n subsets
     (Ryser's subset sum is (-1)^n per(A)), compared exactly.  Real and
-    complex: perm_partial over the same Gray prefix [0, count), the relative
-    error of the double-double result against the long-double sum."""
+    complex: perm_partial over the same Gray prefix [0, count) in the timed
+    precision, the relative error of its result against the long-double sum."""
     from fractions import Fraction
     from paper_1904_06229_amd import binding as B
     if kind == "int01":
@@ -244,7 +259,7 @@ def oracle_check(kind, n, dA, r, count, want):
         return {"range": "whole permanent (all 2^%d subsets)" % n, "checked": True,
                 "exact_match": per == r.exact}
     dAcm = dA.t().contiguous().t()  # the workload's matrix as a column-major view
-    g = B.perm_partial(dAcm, 0, count)
+    g = B.perm_partial(dAcm, 0, count, precision=precision)
     if kind == "complex":
         err = complex_rel_err(g, want)
     else:
@@ -253,7 +268,8 @@ def oracle_check(kind, n, dA, r, count, want):
     whole = count == 1 << (n - 1)
     return {"range": (f"whole half-range sum ({count} Gray terms)" if whole else
                       f"Gray prefix [0, {count}) of 2^{n - 1}"),
-            "checked": True, "rel_err_vs_oracle": err, "tolerance": 1e-10}
+            "checked": True, "precision": precision, "rel_err_vs_oracle": err,
+            "tolerance": 1e-10 if precision != "split" else None}
 
 
 def gpu_qr(G):
@@ -269,7 +285,9 @@ def exact_mean_x2(n, m):
     return math.prod(m / (m + k) for k in range(n))
 
 
-def bench_batched(args):
+def bench_batched(args, standalone=True, sub_frac=0.01):
+    """The batched study: returns its record (and prints it when standalone).
+    sub_frac: the seeded fraction of the batch checked against the oracle."""
     import numpy as np
     import torch
     from paper_1904_06229_amd import binding as B, inputs
@@ -343,7 +361,7 @@ def bench_batched(args):
         import oracle
         oracle.build(force=False)
         rng = np.random.default_rng(seed + 1)
-        pick = rng.choice(count, size=max(1, count // 100), replace=False)
+        pick = rng.choice(count, size=max(1, int(count * sub_frac)), replace=False)
         t3 = time.perf_counter()
         worst = 0.0
         for k in pick:
@@ -354,9 +372,12 @@ def bench_batched(args):
         outj["subsample_max_rel_err"] = worst
         outj["cpu_baseline"] = {"value": len(pick) / odt, "unit": "permanents/s",
                                 "cores": oracle.default_threads(), "kind": "oracle",
-                                "sample": f"{len(pick)} seeded matrices (1%) of the batch, "
-                                          "long-double Ryser", "seconds": round(odt, 2)}
-    print(json.dumps(outj))
+                                "sample": f"{len(pick)} seeded matrices ({sub_frac:.2%}) of "
+                                          "the batch, long-double Ryser",
+                                "seconds": round(odt, 2)}
+    if standalone:
+        print(json.dumps(outj))
+    return outj
 
 
 def bench_repeated(args):
@@ -729,16 +750,14 @@ def bench_sliced(args):
     per_perm = n * float(terms) * run_slices / (slices * args.steps)
     alg = algorithmic_ops_per_term(kind, n) * float(terms) / slices
     kavg = sum(kms) / len(kms) if kms else float("nan")
-    if isinstance(value, tuple):
-        res = repr(complex(float(value[0]), float(value[1])))
-    else:
-        res = repr(float(value))
+    res = str(value.exact) if kind == "int01" else repr(value.value)
     out = {
         "metric": "Gray-code terms/sec (n*2^(n-1)/s)",
         "value": args.steps * per_perm / t_all, "unit": "n*2^(n-1)/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_all * 1e3 / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": DTYPES.get(args.precision, "f64") if kind != "int01" else
+                 "f64 exact-integer + i64 bins", "data": "synthetic",
         "config": {"workload": desc + f", whole permanent as {slices} slices of "
                                       f"{terms // slices} terms",
                    "n": n, "terms": terms, "slices": slices, "precision": args.precision,
@@ -754,8 +773,40 @@ def bench_sliced(args):
     if not args.no_cpu_baseline:
         cb, count, want = cpu_baseline(kind, n, A)
         out["cpu_baseline"] = cb
-        out["oracle_check"] = oracle_check(kind, n, dA, None, count, want)
+        out["oracle_check"] = oracle_check(kind, n, dA, None, count, want,
+                                           args.precision if kind != "int01" else "dd")
     print(json.dumps(out))
+
+
+def compare_precisions(fn, dA, r, timed):
+    """The same whole permanent in the other precisions, once each, outside
+    the timed region: their relative difference to the timed result (the
+    FP64-product kernels are held to 1e-10 against each other; FP32 products
+    are reported)."""
+    from fractions import Fraction
+    out = {}
+    ref = (Fraction(r.re_hi) + Fraction(r.re_lo), Fraction(r.im_hi) + Fraction(r.im_lo))
+    den = math.sqrt(float(ref[0] ** 2 + ref[1] ** 2))
+    for prec in ("dd", "fp64", "split"):
+        if prec == timed:
+            continue
+        g = fn(dA, precision=prec)
+        dr = Fraction(g.re_hi) + Fraction(g.re_lo) - ref[0]
+        di = Fraction(g.im_hi) + Fraction(g.im_lo) - ref[1]
+        out[prec] = {"rel_diff_vs_timed": math.sqrt(float(dr * dr + di * di)) / den,
+                     "kernel_ms": g.kernel_ms, "dtype": DTYPES[prec]}
+    return out
+
+
+def batched_leg(args):
+    """The batched distribution study after the timed region: 100000 Haar
+    blocks, n uniform on 8..24, autotuned, graph replay; 3 timed batches."""
+    a = argparse.Namespace(**vars(args))
+    a.count, a.steps, a.warmup = 100000, 3, 1
+    rec = bench_batched(a, standalone=False, sub_frac=0.001)
+    keep = ("value", "unit", "ms_per_step", "steps", "warmup", "config", "roofline",
+            "subsample_max_rel_err", "cpu_baseline", "mean_X2_vs_exact")
+    return {"metric": rec["metric"], **{k: rec[k] for k in keep if k in rec}}
 
 
 def main():
@@ -819,9 +870,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64 exact-integer + i64 bins" if kind == "int01" else "f64",
+        "dtype": "f64 exact-integer + i64 bins" if kind == "int01" else
+                 DTYPES.get(args.precision, "f64"),
         "data": "synthetic",
         "config": {"workload": desc, "n": n, "terms": terms, "log2_chunk": r.log2_chunk,
+                   "precision": args.precision if kind != "int01" else "exact",
                    "blocks": r.blocks, "walk_variant": r.walk_variant,
                    "col0_nonzeros": r.col0_nonzeros},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
@@ -837,7 +890,12 @@ def main():
     if not args.no_cpu_baseline:
         cb, count, want = cpu_baseline(kind, n, A)
         out["cpu_baseline"] = cb
-        out["oracle_check"] = oracle_check(kind, n, dA, r, count, want)
+        out["oracle_check"] = oracle_check(kind, n, dA, r, count, want,
+                                           args.precision if kind != "int01" else "dd")
+    if kind != "int01" and not args.terms_log2 and not args.no_compare:
+        out["precision_comparison"] = compare_precisions(fn, dA, r, args.precision)
+    if args.workload == "c3" and not args.no_batched:
+        out["batched"] = batched_leg(args)
     print(json.dumps(out))
 
 

@@ -23,8 +23,17 @@
  *     host value; perm_batched only enqueues and returns at once.
  *   - No pointer is kept after a call returns.  Library-owned device
  *     workspace (staged matrix, partial sums, item plans) is allocated lazily per
- *     device and kept until perm_release().  Calls that overlap on one device
- *     (several host threads, or several streams) are not supported.
+ *     device and kept until perm_release().
+ *   - Calls may overlap (several host threads, several streams):
+ *       perm_real, perm_complex, perm_int01, perm_partial each lease a
+ *       workspace of their own for the length of the call (a new one is
+ *       allocated when all are busy), so overlapping calls run concurrently;
+ *       perm_repeated*, perm_sparse*, perm_band take turns on one device (the
+ *       next call enters once the previous one has returned and its stream has
+ *       drained); perm_batched keeps one plan per device and orders its reuse
+ *       by stream: a call on another stream first waits, on the device, for the
+ *       previous call's work.
+ *     perm_release() must not overlap any other call.
  *   - Errors are reported only through the returned status; on error the
  *     outputs are left untouched.  perm_last_error() has a text message.
  *   - n = 0 gives per = 1 (the empty product).  n <= 64.
@@ -153,6 +162,32 @@ typedef enum { PERM_DT_REAL = 0, PERM_DT_COMPLEX = 1, PERM_DT_INT01 = 2 } perm_d
 perm_status perm_partial(int dtype, const void* dA, int n, int ld, uint64_t start,
                          uint64_t count, const perm_opts* opts, perm_result* out,
                          void* stream);
+
+/*
+ * perm_combine -- App. A, permanent: per(A) = 2 (-1)^n sum_k S_k from the
+ * partial sums S_k of perm_partial over ranges that together cover
+ * [0, 2^(n-1)) once (any cut into pieces, e.g. equal slices run one after
+ * another, resumed from a checkpoint, or run on several devices).  Host only.
+ *   dtype, n  as given to perm_partial.
+ *   parts     HOST array of `count` results of perm_partial, in the order of
+ *             their ranges; the sum is taken in exactly that order, so a given
+ *             cut always gives the same bits.
+ *   out       the permanent: re_hi + re_lo (+ i (im_hi + im_lo)), the sum of the
+ *             parts' double-double values by accurate double-double additions, then
+ *             multiplied by 2(-1)^n (exact).  PERM_DT_INT01: the parts' 128-bit
+ *             integers are added modulo 2^128; the total is (-1)^n 2^(n-1) per(A),
+ *             and per(A) is returned exactly in int_lo/int_hi (with its nearest
+ *             double pair in re_hi + re_lo) provided 2^(n-1) per(A) < 2^127
+ *             (check perm_int01_bound on the row sums first: the partial sums
+ *             carry no range check).  terms, chunks, kernel_ms and total_ms are the
+ *             parts' sums, max_drift their maximum; log2_chunk and blocks those
+ *             of parts[0].
+ * Errors: PERM_EINVAL (NULL pointers, bad dtype or n, count < 1, parts whose
+ *   term counts do not add up to 2^(n-1), or 0/1 parts whose total is not a
+ *   multiple of 2^(n-1), i.e. not the whole sum of one matrix).
+ */
+perm_status perm_combine(int dtype, int n, const perm_result* parts, int count,
+                         perm_result* out);
 
 /*
  * perm_batched -- permanents of many independent matrices (the random-matrix

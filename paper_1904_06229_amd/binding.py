@@ -68,6 +68,7 @@ SIGNATURES = {
                        ctypes.POINTER(perm_opts), ctypes.POINTER(perm_result), _vp], _i),
     "perm_repeated_partial": ([_i, _vp, _i, _i, _i, ctypes.POINTER(ctypes.c_int32), _u64, _u64,
                                ctypes.POINTER(perm_opts), ctypes.POINTER(perm_result), _vp], _i),
+    "perm_combine": ([_i, _i, ctypes.POINTER(perm_result), _i, ctypes.POINTER(perm_result)], _i),
     "perm_autotune": ([_i, _i, _i, ctypes.c_char_p, _vp], _i),
     "perm_plan": ([_i, _u64, _u64, _i, _i, ctypes.POINTER(perm_plan_info)], _i),
     "perm_int01_bound": ([ctypes.POINTER(ctypes.c_int32), _i], ctypes.c_double),
@@ -152,9 +153,17 @@ def make_opts(precision="dd", log2_chunk=0, drift_check=False, row_scaling=True,
 
 
 def _stream_handle(stream):
+    """The hipStream_t to enqueue on.  When it is not torch's current stream,
+    it first waits (on the device) for the work already on the current one,
+    so that tensors produced there -- the caller's, or a column-major copy
+    made here -- are complete before the library reads them."""
     import torch
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return ctypes.c_void_p(s.cuda_stream)
+    cur = torch.cuda.current_stream()
+    if stream is None:
+        return ctypes.c_void_p(cur.cuda_stream)
+    if stream != cur:
+        stream.wait_stream(cur)
+    return ctypes.c_void_p(stream.cuda_stream)
 
 
 def _matrix(A, dtype_name):
@@ -231,6 +240,32 @@ def perm_partial(A, start: int, count: int, stream=None, **opts) -> Result:
     o, r = make_opts(**opts), perm_result()
     _check(_lib.perm_partial(dt, p, n, ld, int(start), int(count), ctypes.byref(o),
                              ctypes.byref(r), _stream_handle(stream)), "perm_partial")
+    return _result(r, kind == "int01")
+
+
+def _to_struct(res: Result) -> perm_result:
+    r = perm_result()
+    r.re_hi, r.re_lo, r.im_hi, r.im_lo = res.re_hi, res.re_lo, res.im_hi, res.im_lo
+    if res.exact is not None:
+        v = res.exact & ((1 << 128) - 1)
+        r.int_lo = v & ((1 << 64) - 1)
+        hi = v >> 64
+        r.int_hi = hi - (1 << 64) if hi >= (1 << 63) else hi
+    r.max_drift, r.terms, r.chunks = res.max_drift, res.terms, res.chunks
+    r.log2_chunk, r.blocks = res.log2_chunk, res.blocks
+    r.kernel_ms, r.total_ms = res.kernel_ms, res.total_ms
+    return r
+
+
+def perm_combine(kind: str, n: int, parts) -> Result:
+    """per(A) = 2(-1)^n sum_k S_k from perm_partial results covering the whole
+    range once, added in the given order (App. A, permanent).  kind: "real",
+    "complex" or "int01"."""
+    dt = {"real": PERM_DT_REAL, "complex": PERM_DT_COMPLEX, "int01": PERM_DT_INT01}[kind]
+    parts = list(parts)
+    arr = (perm_result * max(len(parts), 1))(*[_to_struct(p) for p in parts])
+    r = perm_result()
+    _check(_lib.perm_combine(dt, int(n), arr, len(parts), ctypes.byref(r)), "perm_combine")
     return _result(r, kind == "int01")
 
 

@@ -81,10 +81,12 @@ __global__ __launch_bounds__(kBlock) void stage_mix_kernel(const void* __restric
     const int i = tid;
     double mx = 0.0;
     bool bad = false;
+    bool not01 = false;  // 0/1 input: the exact sums assume every entry is 0 or 1
     for (int c = 0; c < nc; ++c)
       for (int p = 0; p < cw; ++p) {
         const double v = load_entry(A, in_kind, ld, dg.row[i], dg.src[c], p);
         if (!isfinite(v)) bad = true;
+        if (in_kind == 2 && v > 1.0) not01 = true;
         mx = fmax(mx, fabs(v));
       }
     int e = 0;
@@ -95,14 +97,20 @@ __global__ __launch_bounds__(kBlock) void stage_mix_kernel(const void* __restric
           const double v = load_entry(A, in_kind, ld, dg.row[i], dg.src[c], p) / mx;
           ss += (double)dg.cmult[c] * v * v;
         }
-      int q;
-      frexp(mx * sqrt(ss), &q);
+      // 2-norm = mx sqrt(ss) in [2^(q-1), 2^q); the exponents of the two
+      // factors are taken apart, so a row near the top of the double range
+      // does not overflow the product
+      int q1, q2;
+      const double f = frexp(mx, &q1) * frexp(sqrt(ss), &q2);  // in [1/4, 1)
+      int q = q1 + q2;
+      if (f < 0.5) --q;
       e = 2 - q;
       e = e < -1000 ? -1000 : (e > 1000 ? 1000 : e);
     }
     s_exp[i] = e;
     rowexp[i] = e;
     if (bad) atomicOr(&s_bad, 1);
+    if (not01) atomicOr(&s_bad, 2);
   }
   __syncthreads();
   const int cols = (nc + 1) * n;  // entries of [+cols | 0]
@@ -200,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void stage_mix_kernel(const void* __restric
     if (cw == 2) staged[o + 1] = si;
   }
   if (tid == 0) {
-    status[0] = s_bad ? kStNonFinite : kStOk;
+    status[0] = (s_bad & 2) ? kStInval : ((s_bad & 1) ? kStNonFinite : kStOk);
     status[1] = 0;
     status[2] = 0;
   }

@@ -76,8 +76,13 @@ __global__ __launch_bounds__(kBlock) void stage_float_kernel(const double* __res
           const double v = s_a[cw * (i + j * n) + c] / mx;
           ss += v * v;
         }
-      int k;
-      frexp(mx * sqrt(ss), &k);  // norm in [2^(k-1), 2^k)
+      // norm = mx sqrt(ss) in [2^(k-1), 2^k); the exponents of the two
+      // factors are taken apart, so a row near the top of the double range
+      // does not overflow the product
+      int k1, k2;
+      const double f = frexp(mx, &k1) * frexp(sqrt(ss), &k2);  // in [1/4, 1)
+      int k = k1 + k2;
+      if (f < 0.5) --k;
       e = 2 - k;
       e = e < -1000 ? -1000 : (e > 1000 ? 1000 : e);
     }

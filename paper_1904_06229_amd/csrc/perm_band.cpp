@@ -28,6 +28,7 @@ struct BandWorkspace {
   char* dmem = nullptr;     // n (int32) then offsets (int64)
   char* hmem = nullptr;     // pinned staging, same layout
   int blocks_per_cu[2][kBandMaxK + 1] = {};  // occupancy by (complex, k); 0 = not queried
+  std::mutex call_mu;       // held for a whole call: calls on one device take turns
 };
 
 std::mutex g_mu;
@@ -42,7 +43,7 @@ size_t layout_bytes(size_t cap, size_t* o_off) {
   return *o_off + cap * sizeof(int64_t);
 }
 
-perm_status get_ws(size_t count, BandWorkspace** out) {
+perm_status get_ws(BandWorkspace** out) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail("hipGetDevice", e);
@@ -55,28 +56,42 @@ perm_status get_ws(size_t count, BandWorkspace** out) {
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
       w->cu_count = prop.multiProcessorCount;
   }
-  if (w->cap < count) {
-    size_t cap = 1024;
-    while (cap < count) cap *= 2;
-    size_t o_off;
-    const size_t bytes = layout_bytes(cap, &o_off);
-    char* d = nullptr;
-    char* h = nullptr;
-    if (hipMalloc((void**)&d, bytes) != hipSuccess)
-      return set_error(PERM_ENOMEM, "hipMalloc of the band workspace failed");
-    if (hipHostMalloc((void**)&h, bytes, hipHostMallocDefault) != hipSuccess) {
-      (void)hipFree(d);
-      return set_error(PERM_ENOMEM, "hipHostMalloc of the band staging failed");
-    }
-    if (w->dmem) (void)hipFree(w->dmem);
-    if (w->hmem) (void)hipHostFree(w->hmem);
-    w->dmem = d;
-    w->hmem = h;
-    w->cap = cap;
-  }
   *out = w;
   return PERM_OK;
 }
+
+// Grows the size/offset buffers to hold `count` matrices.  Called with the
+// workspace's call lock held, after the previous call's stream has drained.
+perm_status ensure_cap(BandWorkspace* w, size_t count) {
+  if (w->cap >= count) return PERM_OK;
+  size_t cap = 1024;
+  while (cap < count) cap *= 2;
+  size_t o_off;
+  const size_t bytes = layout_bytes(cap, &o_off);
+  char* d = nullptr;
+  char* h = nullptr;
+  if (hipMalloc((void**)&d, bytes) != hipSuccess)
+    return set_error(PERM_ENOMEM, "hipMalloc of the band workspace failed");
+  if (hipHostMalloc((void**)&h, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipFree(d);
+    return set_error(PERM_ENOMEM, "hipHostMalloc of the band staging failed");
+  }
+  if (w->dmem) (void)hipFree(w->dmem);
+  if (w->hmem) (void)hipHostFree(w->hmem);
+  w->dmem = d;
+  w->hmem = h;
+  w->cap = cap;
+  return PERM_OK;
+}
+
+// Holds a device's workspace for the length of one call; on the way out
+// (also after an error) the stream is drained before the next call enters.
+struct CallGuard {
+  std::unique_lock<std::mutex> lk;
+  hipStream_t s;
+  CallGuard(BandWorkspace* w, hipStream_t st) : lk(w->call_mu), s(st) {}
+  ~CallGuard() { (void)hipStreamSynchronize(s); }
+};
 
 }  // namespace
 
@@ -120,8 +135,10 @@ extern "C" perm_status perm_band(int dtype, const double* dA, const int32_t* h_n
     if (h_offset[m] < 0) return set_error(PERM_EINVAL, "offsets must be >= 0");
   }
   BandWorkspace* ws = nullptr;
-  perm_status st = get_ws((size_t)count, &ws);
+  perm_status st = get_ws(&ws);
   if (st != PERM_OK) return st;
+  CallGuard guard(ws, (hipStream_t)stream);
+  if ((st = ensure_cap(ws, (size_t)count)) != PERM_OK) return st;
   size_t o_off;
   const size_t bytes = layout_bytes(ws->cap, &o_off);
   std::memcpy(ws->hmem, h_n, sizeof(int32_t) * count);

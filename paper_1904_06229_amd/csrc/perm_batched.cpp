@@ -70,6 +70,12 @@ struct Plan {
   std::vector<Group> groups;  // by size, largest first
   hipGraphExec_t gexec = nullptr;
   hipStream_t gstream = nullptr;
+  // Stream order of the plan's buffers: `done` is recorded after each call's
+  // work; a call on another stream first waits for it, and the buffers are
+  // freed only once it has completed.
+  hipEvent_t done = nullptr;
+  hipStream_t last = nullptr;
+  bool used = false;
 };
 
 std::vector<Plan*> g_plans;  // one per device
@@ -77,6 +83,10 @@ int g_tune_stamp = 0;
 
 void free_plan(Plan* p) {
   if (!p) return;
+  if (p->done) {
+    if (p->used) (void)hipEventSynchronize(p->done);
+    (void)hipEventDestroy(p->done);
+  }
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
   if (p->mem) (void)hipFree(p->mem);
   delete p;
@@ -232,6 +242,35 @@ perm_status enqueue(Plan* p, hipStream_t s) {
   return PERM_OK;
 }
 
+// The plan's launches on s: directly, or as a HIP graph captured once per
+// stream and replayed.
+perm_status launch_plan(Plan* p, hipStream_t s, bool use_graph) {
+  if (!use_graph) return enqueue(p, s);
+  if (!p->gexec || p->gstream != s) {
+    if (p->gexec) {
+      (void)hipGraphExecDestroy(p->gexec);
+      p->gexec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return set_error(PERM_EHIP, "hipStreamBeginCapture failed (graphs need a non-default stream)");
+    perm_status st = enqueue(p, s);
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (st != PERM_OK) return st;
+    if (e != hipSuccess) return set_error(PERM_EHIP, "hipStreamEndCapture failed");
+    e = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      p->gexec = nullptr;
+      return set_error(PERM_EHIP, "hipGraphInstantiate failed");
+    }
+    p->gstream = s;
+  }
+  if (hipGraphLaunch(p->gexec, s) != hipSuccess) return set_error(PERM_EHIP, "hipGraphLaunch failed");
+  return PERM_OK;
+}
+
+
 // ------------------------------------------------------------ tune cache ----
 
 void write_cache(const char* path) {
@@ -344,34 +383,30 @@ perm_status perm_batched(const double* dA, const int32_t* h_n, const int64_t* h_
     p->off.assign(h_offset, h_offset + count);
     p->tune_stamp = g_tune_stamp;
     perm_status st = build_plan(p, dev);
+    if (st == PERM_OK && hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess) {
+      p->done = nullptr;
+      st = set_error(PERM_EHIP, "hipEventCreate failed");
+    }
     if (st != PERM_OK) {
       free_plan(p);
       return st;
     }
     g_plans.push_back(p);
   }
-  if (!o.use_graph) return enqueue(p, s);
-  if (!p->gexec || p->gstream != s) {
-    if (p->gexec) {
-      (void)hipGraphExecDestroy(p->gexec);
-      p->gexec = nullptr;
-    }
-    hipGraph_t g = nullptr;
-    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
-      return set_error(PERM_EHIP, "hipStreamBeginCapture failed (graphs need a non-default stream)");
-    perm_status st = enqueue(p, s);
-    hipError_t e = hipStreamEndCapture(s, &g);
-    if (st != PERM_OK) return st;
-    if (e != hipSuccess) return set_error(PERM_EHIP, "hipStreamEndCapture failed");
-    e = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) {
-      p->gexec = nullptr;
-      return set_error(PERM_EHIP, "hipGraphInstantiate failed");
-    }
-    p->gstream = s;
+  if (p->used && p->last != s && hipStreamWaitEvent(s, p->done, 0) != hipSuccess)
+    return set_error(PERM_EHIP, "hipStreamWaitEvent failed");
+  perm_status st = launch_plan(p, s, o.use_graph != 0);
+  if (st != PERM_OK) return st;
+  if (hipEventRecord(p->done, s) != hipSuccess) {
+    // the order of later calls can no longer be kept: drain and forget the plan
+    (void)hipStreamSynchronize(s);
+    g_plans.erase(std::find(g_plans.begin(), g_plans.end(), p));
+    p->used = false;
+    free_plan(p);
+    return set_error(PERM_EHIP, "hipEventRecord failed");
   }
-  if (hipGraphLaunch(p->gexec, s) != hipSuccess) return set_error(PERM_EHIP, "hipGraphLaunch failed");
+  p->last = s;
+  p->used = true;
   return PERM_OK;
 }
 

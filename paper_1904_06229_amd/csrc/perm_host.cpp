@@ -61,20 +61,25 @@ struct Workspace {
   double* drift = nullptr;
 };
 
+// Workspaces are leased, one per call: a call takes an idle workspace of the
+// current device (or allocates one) and gives it back when it returns, after
+// its stream has finished with it.  Calls from several host threads or on
+// several streams therefore never share device buffers.
 std::mutex g_mu;
-std::map<int, Workspace*> g_ws;
+std::map<int, std::vector<Workspace*>> g_idle;  // idle workspaces per device
+std::vector<Workspace*> g_all;                  // every workspace, for perm_release
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-perm_status get_workspace(Workspace** out) {
-  int dev = 0;
-  HIP_TRY(hipGetDevice(&dev));
-  std::lock_guard<std::mutex> lk(g_mu);
-  auto it = g_ws.find(dev);
-  if (it != g_ws.end()) {
-    *out = it->second;
-    return PERM_OK;
-  }
+void destroy_workspace(Workspace* w) {
+  for (auto& ev : w->ev)
+    if (ev) (void)hipEventDestroy(ev);
+  if (w->hres) (void)hipHostFree(w->hres);
+  if (w->dmem) (void)hipFree(w->dmem);
+  delete w;
+}
+
+perm_status create_workspace(int dev, Workspace** out) {
   Workspace* w = new Workspace();
   w->device = dev;
   size_t off = 0;
@@ -96,27 +101,30 @@ perm_status get_workspace(Workspace** out) {
   off = align_up(off + sizeof(double) * (size_t)kMaxParts, 256);
   hipError_t e = hipMalloc((void**)&w->dmem, off);
   if (e != hipSuccess) {
-    delete w;
+    w->dmem = nullptr;
+    destroy_workspace(w);
     return fail(PERM_ENOMEM, std::string("hipMalloc of workspace failed: ") + hipGetErrorString(e));
   }
   e = hipHostMalloc((void**)&w->hres, sizeof(DevResult), hipHostMallocDefault);
   if (e != hipSuccess) {
-    (void)hipFree(w->dmem);
-    delete w;
+    w->hres = nullptr;
+    destroy_workspace(w);
     return fail(PERM_ENOMEM, std::string("hipHostMalloc failed: ") + hipGetErrorString(e));
   }
   // The finishing kernel writes the result record straight into pinned host
   // memory (no separate copy); the stream synchronisation makes it visible.
   e = hipHostGetDevicePointer((void**)&w->hres_dev, w->hres, 0);
   if (e != hipSuccess) {
-    (void)hipHostFree(w->hres);
-    (void)hipFree(w->dmem);
-    delete w;
+    destroy_workspace(w);
     return fail(PERM_EHIP, std::string("hipHostGetDevicePointer failed: ") + hipGetErrorString(e));
   }
   for (auto& ev : w->ev) {
     e = hipEventCreate(&ev);
-    if (e != hipSuccess) return fail(PERM_EHIP, std::string("hipEventCreate failed: ") + hipGetErrorString(e));
+    if (e != hipSuccess) {
+      ev = nullptr;
+      destroy_workspace(w);
+      return fail(PERM_EHIP, std::string("hipEventCreate failed: ") + hipGetErrorString(e));
+    }
   }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) == hipSuccess)
@@ -130,10 +138,45 @@ perm_status get_workspace(Workspace** out) {
   w->staged = (double*)(w->dmem + o_staged);
   w->partials = (void*)(w->dmem + o_part);
   w->drift = (double*)(w->dmem + o_drift);
-  g_ws[dev] = w;
   *out = w;
   return PERM_OK;
 }
+
+perm_status acquire_workspace(Workspace** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    std::vector<Workspace*>& idle = g_idle[dev];
+    if (!idle.empty()) {
+      *out = idle.back();
+      idle.pop_back();
+      return PERM_OK;
+    }
+  }
+  Workspace* w = nullptr;
+  perm_status st = create_workspace(dev, &w);
+  if (st != PERM_OK) return st;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_all.push_back(w);
+  *out = w;
+  return PERM_OK;
+}
+
+// A leased workspace.  It goes back to the idle list when the call returns;
+// if work was enqueued and the call is leaving early (an error after a
+// launch), the stream is drained first so that no kernel still uses it.
+struct Lease {
+  Workspace* w = nullptr;
+  hipStream_t s = nullptr;
+  bool pending = false;
+  ~Lease() {
+    if (!w) return;
+    if (pending) (void)hipStreamSynchronize(s);
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_idle[w->device].push_back(w);
+  }
+};
 
 uint64_t total_terms(int n) { return n >= 64 ? (1ull << 63) : (1ull << (n - 1)); }
 
@@ -210,9 +253,11 @@ perm_status run_range(int kind, const void* dA, int n, int ld, uint64_t start, u
   perm_plan_info plan;
   perm_status st = perm_plan(n, start, count, o.log2_chunk, is_int, &plan);
   if (st != PERM_OK) return st;
-  Workspace* ws = nullptr;
-  st = get_workspace(&ws);
+  Lease lease;
+  st = acquire_workspace(&lease.w);
   if (st != PERM_OK) return st;
+  Workspace* ws = lease.w;
+  lease.s = s;
   // 8 workgroups (32 waves) per CU: more than can be resident, so the
   // dispatcher hands out the remaining workgroups as others finish, which
   // evens out the tail.
@@ -228,6 +273,7 @@ perm_status run_range(int kind, const void* dA, int n, int ld, uint64_t start, u
   // Only the walk is timed with events (each record is a marker packet in the
   // stream, a few microseconds of gap); the whole call is timed on the host.
   const auto t_call = std::chrono::steady_clock::now();
+  lease.pending = true;
   HIP_TRY(launch_stage(kind, dA, n, ld, o.no_row_scaling ? 0 : 1, range_check, pair_rows,
                        ws->staged, ws->rowabs, ws->rowexp, ws->status, ws->bound, s));
 
@@ -267,6 +313,7 @@ perm_status run_range(int kind, const void* dA, int n, int ld, uint64_t start, u
   HIP_TRY(launch_finish(kind, ws->partials, nparts, ws->drift, drift ? 1 : 0, ws->status,
                         ws->rowexp, n, ws->bound, ws->hres_dev, s));
   HIP_TRY(hipStreamSynchronize(s));
+  lease.pending = false;
   raw->r = *ws->hres;
   raw->plan = plan;
   raw->blocks = body_grid;
@@ -308,6 +355,29 @@ void pair_from_i128(__int128 v, double* hi, double* lo) {
     return;
   }
   *lo = (double)(v - (__int128)h);
+}
+
+// Accurate double-double addition on the host (two TwoSums and two
+// renormalisations, as the device reductions).  This file is compiled with
+// -ffp-contract=off, so nothing is fused.
+struct HostDD {
+  double hi, lo;
+};
+
+HostDD host_dd_add(HostDD a, HostDD b) {
+  double s = a.hi + b.hi;
+  double bs = s - a.hi;
+  double e = (a.hi - (s - bs)) + (b.hi - bs);
+  double t = a.lo + b.lo;
+  double bt = t - a.lo;
+  double f = (a.lo - (t - bt)) + (b.lo - bt);
+  e += t;
+  double s2 = s + e;
+  e = e - (s2 - s);
+  e += f;
+  double s3 = s2 + e;
+  e = e - (s3 - s2);
+  return HostDD{s3, e};
 }
 
 perm_status float_call(int kind, const double* dA, int n, int ld, const perm_opts* opts,
@@ -476,6 +546,62 @@ perm_status perm_partial(int dtype, const void* dA, int n, int ld, uint64_t star
   return PERM_OK;
 }
 
+perm_status perm_combine(int dtype, int n, const perm_result* parts, int count,
+                         perm_result* out) {
+  if (!out || !parts) return fail(PERM_EINVAL, "NULL argument");
+  if (dtype < 0 || dtype > 2) return fail(PERM_EINVAL, "dtype must be 0, 1 or 2");
+  if (n < 1 || n > kMaxN) return fail(PERM_EINVAL, "n must be in [1, 64]");
+  if (count < 1) return fail(PERM_EINVAL, "count must be >= 1");
+  const uint64_t T = total_terms(n);
+  uint64_t terms = 0, chunks = 0;
+  double drift = -1.0;
+  float kms = 0.0f, tms = 0.0f;
+  for (int k = 0; k < count; ++k) {
+    if (parts[k].terms > T - terms) return fail(PERM_EINVAL, "the parts hold more than 2^(n-1) terms");
+    terms += parts[k].terms;
+    chunks += parts[k].chunks;
+    drift = std::max(drift, parts[k].max_drift);
+    kms += parts[k].kernel_ms;
+    tms += parts[k].total_ms;
+  }
+  if (terms != T) return fail(PERM_EINVAL, "the parts do not cover all 2^(n-1) terms");
+  perm_result r{};
+  r.terms = T;
+  r.chunks = chunks;
+  r.max_drift = drift;
+  r.kernel_ms = kms;
+  r.total_ms = tms;
+  r.log2_chunk = parts[0].log2_chunk;
+  r.blocks = parts[0].blocks;
+  if (dtype == PERM_DT_INT01) {
+    // The parts hold sum (-1)^(g+1) prod_i r_i = (-1)^n 2^(n-1) per(A), mod 2^128.
+    unsigned __int128 u = 0;
+    for (int k = 0; k < count; ++k)
+      u += ((unsigned __int128)(uint64_t)parts[k].int_hi << 64) | parts[k].int_lo;
+    const unsigned __int128 low_mask = (((unsigned __int128)1) << (n - 1)) - 1;
+    if ((u & low_mask) != 0)
+      return fail(PERM_EINVAL, "the parts do not add up to a multiple of 2^(n-1)");
+    __int128 per = ((__int128)u) >> (n - 1);
+    if (n % 2) per = -per;
+    r.int_lo = (uint64_t)(unsigned __int128)per;
+    r.int_hi = (int64_t)(per >> 64);
+    pair_from_i128(per, &r.re_hi, &r.re_lo);
+  } else {
+    HostDD re{0.0, 0.0}, im{0.0, 0.0};
+    for (int k = 0; k < count; ++k) {
+      re = host_dd_add(re, HostDD{parts[k].re_hi, parts[k].re_lo});
+      im = host_dd_add(im, HostDD{parts[k].im_hi, parts[k].im_lo});
+    }
+    const double f = (n % 2 == 0) ? 2.0 : -2.0;  // per = 2 (-1)^n S
+    r.re_hi = f * re.hi;
+    r.re_lo = f * re.lo;
+    r.im_hi = f * im.hi;
+    r.im_lo = f * im.lo;
+  }
+  *out = r;
+  return PERM_OK;
+}
+
 const char* perm_strerror(perm_status s) {
   switch (s) {
     case PERM_OK: return "success";
@@ -497,17 +623,13 @@ void perm_release(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   int cur = 0;
   (void)hipGetDevice(&cur);
-  for (auto& kv : g_ws) {
-    Workspace* w = kv.second;
+  for (Workspace* w : g_all) {
     (void)hipSetDevice(w->device);
     (void)hipDeviceSynchronize();
-    for (auto& ev : w->ev)
-      if (ev) (void)hipEventDestroy(ev);
-    if (w->hres) (void)hipHostFree(w->hres);
-    if (w->dmem) (void)hipFree(w->dmem);
-    delete w;
+    destroy_workspace(w);
   }
-  g_ws.clear();
+  g_all.clear();
+  g_idle.clear();
   perm::batched_release();
   perm::repeated_release();
   perm::band_release();

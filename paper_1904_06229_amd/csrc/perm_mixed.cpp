@@ -47,10 +47,22 @@ struct MixWorkspace {
   double* tin = nullptr;
   int32_t* toff = nullptr;
   void* partials = nullptr;
+  std::mutex call_mu;  // held for a whole call: calls on one device take turns
 };
 
 std::mutex g_mu;
 std::map<int, MixWorkspace*> g_ws;
+
+// Holds a device's workspace for the length of one call.  On the way out
+// (also after an error) the stream is drained before the next call may
+// enter, so a call on another stream or thread never finds kernels of this
+// one still using the buffers.
+struct CallGuard {
+  std::unique_lock<std::mutex> lk;
+  hipStream_t s;
+  CallGuard(MixWorkspace* w, hipStream_t st) : lk(w->call_mu), s(st) {}
+  ~CallGuard() { (void)hipStreamSynchronize(s); }
+};
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -280,6 +292,8 @@ perm_status run_mixed(MixWorkspace* ws, int in_kind, const void* dA, int n, int 
   (void)hipEventElapsedTime(&wk->total_ms, ws->ev[0], ws->ev[3]);
   if (wk->res.status == kStNonFinite)
     return set_error(PERM_ENONFINITE, "matrix has a NaN or infinite entry");
+  if (wk->res.status == kStInval)
+    return set_error(PERM_EINVAL, "0/1 matrix has an entry other than 0 or 1");
   if (wk->res.status != kStOk) return set_error(PERM_EHIP, "unexpected device status");
   return PERM_OK;
 }
@@ -360,6 +374,7 @@ perm_status rep_call(int dtype, const double* dC, int n, int R, int ld, const in
   }
   MixWorkspace* ws = nullptr;
   if ((st = get_ws(&ws)) != PERM_OK) return st;
+  CallGuard guard(ws, stream);
   Walked wk;
   st = run_mixed(ws, dtype == PERM_DT_COMPLEX ? 1 : 0, dC, n, ld, dg, start, count, o,
                  o.no_row_scaling ? 0 : 1, false, 0, stream, &wk);
@@ -431,6 +446,7 @@ perm_status sparse_call(int dtype, const void* dA, int n, int ld, int trials, ui
   if ((st = check_opts(o)) != PERM_OK) return st;
   MixWorkspace* ws = nullptr;
   if ((st = get_ws(&ws)) != PERM_OK) return st;
+  CallGuard guard(ws, stream);
   SparsePart p;
   if ((st = partition(ws, dtype, dA, n, ld, trials, seed, stream, &p)) != PERM_OK) return st;
   perm_result r{};
@@ -545,6 +561,7 @@ perm_status perm_sparse_partition(int dtype, const void* dA, int n, int ld, int 
   if (!block_of_col || !nblocks || !terms) return set_error(PERM_EINVAL, "NULL argument");
   MixWorkspace* ws = nullptr;
   if ((st = get_ws(&ws)) != PERM_OK) return st;
+  CallGuard guard(ws, (hipStream_t)stream);
   SparsePart p;
   if ((st = partition(ws, dtype, dA, n, ld, trials, seed, (hipStream_t)stream, &p)) != PERM_OK)
     return st;

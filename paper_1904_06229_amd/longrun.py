@@ -11,8 +11,10 @@ where it stopped and, because the order of the final sum is fixed, finishes
 with the same bits.  This is also how the range would be divided between
 devices.
 
-The only host arithmetic is the final sum of the slice partials (exact, as
-rationals) and the factor 2(-1)^n of App. A, permanent.
+The slice sums are combined by the library's perm_combine (App. A,
+permanent: per = 2(-1)^n sum_k S_k, the parts added in slice order in
+double-double, or as 128-bit integers for 0/1 input); this module only runs
+the slices and keeps the checkpoint.
 """
 from __future__ import annotations
 
@@ -20,7 +22,6 @@ import hashlib
 import json
 import os
 import time
-from fractions import Fraction
 
 from . import binding as B
 
@@ -36,10 +37,10 @@ def fingerprint(A) -> str:
 
 
 def run_sliced(A, slices: int = 16, checkpoint: str | None = None, progress=None, **opts):
-    """per(A) from `slices` perm_partial launches.  Returns (value, info).
+    """per(A) from `slices` perm_partial launches.  Returns (result, info).
 
-    value: Fraction (real, 0/1: exact int via the 2^n factor) or a pair of
-    Fractions (complex).  info: per-slice seconds and walk-kernel
+    result: the library's Result of perm_combine over the slices (``.value``;
+    ``.exact`` for 0/1 input).  info: per-slice seconds and walk-kernel
     milliseconds of the slices run now, and the number resumed.
     `opts` go to perm_partial (blocks, log2_chunk, precision, stream).
     """
@@ -73,25 +74,22 @@ def run_sliced(A, slices: int = 16, checkpoint: str | None = None, progress=None
         rec = {"slice": k, "slices": slices, "fingerprint": fp, "kind": kind,
                "re": [r.re_hi, r.re_lo], "im": [r.im_hi, r.im_lo],
                "exact": None if r.exact is None else str(r.exact), "seconds": dt,
-               "kernel_ms": r.kernel_ms, "max_drift": r.max_drift}
+               "kernel_ms": r.kernel_ms, "max_drift": r.max_drift, "terms": r.terms,
+               "chunks": r.chunks, "log2_chunk": r.log2_chunk, "blocks": r.blocks}
         done[k] = rec
         if checkpoint:
             with open(checkpoint, "a") as f:
                 f.write(json.dumps(rec) + "\n")
         if progress:
             progress(f"slice {k + 1}/{slices} done in {dt:.1f} s")
-    sign = 2 if n % 2 == 0 else -2  # per = 2 (-1)^n S
-    if kind == "int01":
-        S = sum(int(done[k]["exact"]) for k in range(slices))  # = 2^n * S (integer form)
-        S %= 1 << 128
-        if S >= 1 << 127:
-            S -= 1 << 128
-        value = Fraction(sign * S, 1 << n)
-        return value, {"seconds": secs, "kernel_ms": kms, "resumed": resumed}
-    re = sum((Fraction(done[k]["re"][0]) + Fraction(done[k]["re"][1]) for k in range(slices)),
-             Fraction(0))
-    im = sum((Fraction(done[k]["im"][0]) + Fraction(done[k]["im"][1]) for k in range(slices)),
-             Fraction(0))
-    if kind == "real":
-        return sign * re, {"seconds": secs, "kernel_ms": kms, "resumed": resumed}
-    return (sign * re, sign * im), {"seconds": secs, "kernel_ms": kms, "resumed": resumed}
+    parts = []
+    for k in range(slices):
+        rec = done[k]
+        parts.append(B.Result(rec["re"][0], rec["re"][1], rec["im"][0], rec["im"][1],
+                              None if rec["exact"] is None else int(rec["exact"]),
+                              rec.get("max_drift", -1.0), rec.get("terms", width),
+                              rec.get("chunks", 0), rec.get("log2_chunk", 0),
+                              rec.get("blocks", 0), rec.get("kernel_ms", 0.0),
+                              1e3 * rec.get("seconds", 0.0)))
+    result = B.perm_combine(kind, n, parts)
+    return result, {"seconds": secs, "kernel_ms": kms, "resumed": resumed}

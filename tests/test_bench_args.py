@@ -22,14 +22,16 @@ def parse(argv, monkeypatch):
 
 
 def test_defaults(monkeypatch):
-    assert parse([], monkeypatch) == (20, 3)
+    assert parse([], monkeypatch) == (5, 1)  # the 40 x 40 complex workload, ~4 s a step
     assert parse(["--workload", "c3"], monkeypatch) == (5, 1)
+    assert parse(["--workload", "c2"], monkeypatch) == (20, 3)
     assert parse(["--workload", "c8"], monkeypatch) == (3, 1)
     assert parse(["--workload", "c5", "--terms-log2", "30"], monkeypatch) == (20, 3)
     assert parse(["--workload", "c5"], monkeypatch) == (1, 0)
     assert parse(["--slices", "4"], monkeypatch) == (1, 0)
     assert parse(["--workload", "c5", "--checkpoint", "ck.jsonl"], monkeypatch) == (1, 0)
     assert parse(["--steps", "5", "--warmup", "0"], monkeypatch) == (5, 0)
+    assert parse(["--steps", "20", "--warmup", "5"], monkeypatch) == (20, 5)
 
 
 @pytest.mark.parametrize("argv", [["--workload", "c5", "--checkpoint", "c", "--steps", "2"],

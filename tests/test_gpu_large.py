@@ -139,30 +139,3 @@ def test_split_precision_reported_error(B, orc, inp):
         sp = rel(val(B.perm_complex(dev_cm(A), precision="split")), want)
         log(f"  n={n}: FP64 {dd:.2e}  FP32-product {sp:.2e}")
         assert dd < TOL and sp < 1e-3
-
-
-def test_complex40_whole_equals_split_partials(B, inp):
-    """The benchmarked 40 x 40 Haar block, whole, in the benchmark's call
-    (perm_complex with default options on the row-major array, i.e. on A^T,
-    whose permanent is the same), against the sum of three partial ranges of
-    A's Gray enumeration with unaligned cuts: per = 2 S for even n.  The two
-    chunkings start their walks at different terms, so their row sums carry
-    different rounding, which the cancellation in the sum amplifies (about
-    4e-12 here); the bar is the FP64 one, 1e-10 relative."""
-    from fractions import Fraction
-    n = 40
-    A = inp.haar_block(n, n * n, 20190402)
-    T = 1 << (n - 1)
-    log("40x40 complex: whole permanent, then three partial ranges")
-    whole = B.perm_complex(torch.from_numpy(np.ascontiguousarray(A)).to("cuda"))
-    cuts = [0, T // 3 + 12345, (2 * T) // 3 - 77, T]
-    re = im = Fraction(0)
-    dA = dev_cm(A)
-    for a, b in zip(cuts[:-1], cuts[1:]):
-        p = B.perm_partial(dA, a, b - a)
-        re += Fraction(p.re_hi) + Fraction(p.re_lo)
-        im += Fraction(p.im_hi) + Fraction(p.im_lo)
-    per = complex(float(2 * re), float(2 * im))
-    got = complex(whole.re_hi + whole.re_lo, whole.im_hi + whole.im_lo)
-    log(f"40x40 complex: per = {got:.6e}, rel diff to the split sum {rel(got, per):.2e}")
-    assert rel(got, per) < TOL

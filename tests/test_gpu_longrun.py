@@ -32,9 +32,9 @@ def test_sliced_real_and_complex(mods, orc):
         log(f"n={n}: 16 slices, {sum(info['seconds']):.3f} s")
         w = orc.ryser(A)
         if A.dtype == np.float64:
-            got, want, one = float(v), float(w.exact), whole.re_hi + whole.re_lo
+            got, want, one = v.re_hi + v.re_lo, float(w.exact), whole.re_hi + whole.re_lo
         else:
-            got = complex(float(v[0]), float(v[1]))
+            got = complex(v.re_hi + v.re_lo, v.im_hi + v.im_lo)
             want = complex(float(w.re.exact), float(w.im.exact))
             one = complex(whole.re_hi + whole.re_lo, whole.im_hi + whole.im_lo)
         assert abs(got - want) <= 1e-10 * abs(want)
@@ -49,11 +49,11 @@ def test_sliced_int01_exact_and_resume(mods, orc, tmp_path):
     want = orc.ryser(A)
     ck = tmp_path / "ck.jsonl"
     v, _ = lr.run_sliced(dA, slices=32, checkpoint=str(ck))
-    assert v == want == B.perm_int01(dA).exact
+    assert v.exact == want == B.perm_int01(dA).exact
     lines = ck.read_text().splitlines()
     ck.write_text("\n".join(lines[:20]) + "\n")
     v2, info = lr.run_sliced(dA, slices=32, checkpoint=str(ck))
-    assert info["resumed"] == 20 and v2 == v
+    assert info["resumed"] == 20 and v2.exact == v.exact
 
 
 def test_sliced_real_resume_same_bits(mods, tmp_path):
@@ -65,6 +65,7 @@ def test_sliced_real_resume_same_bits(mods, tmp_path):
     lines = ck.read_text().splitlines()
     ck.write_text("\n".join(lines[:5]) + "\n")
     v2, info = lr.run_sliced(dA, slices=8, checkpoint=str(ck))
-    assert info["resumed"] == 5 and v1 == v2
+    bits = lambda r: (r.re_hi, r.re_lo, r.im_hi, r.im_lo)
+    assert info["resumed"] == 5 and bits(v1) == bits(v2)
     v3, _ = lr.run_sliced(dA, slices=8)  # fresh run: the walk is bit-reproducible
-    assert v3 == v1
+    assert bits(v3) == bits(v1)

@@ -1,10 +1,11 @@
 """Host logic of the sliced long-run driver, on the CPU.
 
-``run_sliced`` only divides the Gray range, keeps the checkpoint and adds the
-slice partials with the factor 2(-1)^n of App. A (permanent).  Here the
-library call is replaced, inside the test only, by the oracle's partial sum
-over the same range, so the slicing, resume and final sum are checked against
-the oracle's whole permanent without a GPU.
+``run_sliced`` only divides the Gray range and keeps the checkpoint; the
+slice partials are added, with the factor 2(-1)^n of App. A (permanent), by
+the library's host-only ``perm_combine``.  Here the GPU call is replaced,
+inside the test only, by the oracle's partial sum over the same range, so the
+slicing, resume and the C-ABI's final sum are checked against the oracle's
+whole permanent without a GPU.
 """
 import json
 
@@ -54,13 +55,15 @@ def test_sliced_equals_whole(lr, orc, n, kind):
     for slices in sorted({1, min(2, T), min(4, T), T}):
         v, info = lr.run_sliced(torch.from_numpy(A), slices=slices)
         assert info["resumed"] == 0 and len(info["kernel_ms"]) == slices
+        assert v.terms == T
         if kind == "int01":
-            assert v == want
+            assert v.exact == want
         elif kind == "real":
-            assert abs(float(v) - float(want.exact)) <= 1e-12 * max(1.0, abs(float(want.exact)))
+            assert abs(v.value - float(want.exact)) <= 1e-12 * max(1.0, abs(float(want.exact)))
         else:
             w = complex(float(want.re.exact), float(want.im.exact))
-            assert abs(complex(float(v[0]), float(v[1])) - w) <= 1e-12 * max(1.0, abs(w))
+            got = complex(v.re_hi + v.re_lo, v.im_hi + v.im_lo)
+            assert abs(got - w) <= 1e-12 * max(1.0, abs(w))
 
 
 def test_slices_cover_range_once(lr):
@@ -80,7 +83,8 @@ def test_resume_skips_done_slices_and_keeps_bits(lr, tmp_path):
     lr.calls.clear()
     v2, info = lr.run_sliced(A, slices=8, checkpoint=str(ck))
     assert info["resumed"] == 3 and [c[0] for c in lr.calls] == [k * 32 for k in range(3, 8)]
-    assert v1 == v2  # exact Fractions: same bits after resume
+    bits = lambda r: (r.re_hi, r.re_lo, r.im_hi, r.im_lo)
+    assert bits(v1) == bits(v2)  # fixed order of the final sum: same bits after resume
 
 
 def test_checkpoint_of_other_matrix_ignored(lr, tmp_path):
@@ -100,3 +104,37 @@ def test_checkpoint_of_other_matrix_ignored(lr, tmp_path):
 def test_bad_slices(lr, slices):
     with pytest.raises(ValueError):
         lr.run_sliced(torch.from_numpy(mats(6, 1)["real"]), slices=slices)
+
+
+def test_combine_rejects_incomplete_or_inconsistent_parts(orc):
+    """perm_combine checks that the parts cover the 2^(n-1) terms once, and for
+    0/1 input that the total is a multiple of 2^(n-1)."""
+    from paper_1904_06229_amd import binding as B
+    A = mats(6, 2)["int01"]
+    kw = dict(max_drift=-1.0, chunks=1, log2_chunk=0, blocks=1, kernel_ms=0.0, total_ms=0.0)
+    parts = [B.Result(0.0, 0.0, 0.0, 0.0, orc.chunk_partial(A, k * 8, 8), terms=8, **kw)
+             for k in range(4)]
+    assert B.perm_combine("int01", 6, parts).exact == orc.ryser(A)
+    with pytest.raises(B.PermError):
+        B.perm_combine("int01", 6, parts[:3])  # 24 of 32 terms
+    bad = list(parts)
+    bad[0] = B.Result(0.0, 0.0, 0.0, 0.0, parts[0].exact + 1, terms=8, **kw)
+    with pytest.raises(B.PermError):
+        B.perm_combine("int01", 6, bad)  # not a multiple of 2^5
+    with pytest.raises(B.PermError):
+        B.perm_combine("real", 6, parts + parts[:1])  # more than 2^(n-1) terms
+
+
+def test_combine_sign_and_order():
+    """2(-1)^n S, with the parts added as double-double pairs: parts that
+    cancel to far below their own size keep their low words."""
+    from paper_1904_06229_amd import binding as B
+    kw = dict(max_drift=-1.0, chunks=1, log2_chunk=0, blocks=1, kernel_ms=0.0, total_ms=0.0)
+    p = [B.Result(2.0 ** 40, 0.0, 0.0, 0.0, None, terms=2, **kw),
+         B.Result(3.0, 2.0 ** -60, -1.0, 0.0, None, terms=1, **kw),
+         B.Result(-(2.0 ** 40), 0.0, 0.5, 0.0, None, terms=1, **kw)]
+    odd = B.perm_combine("complex", 3, p)  # n = 3: factor -2
+    assert (odd.re_hi, odd.re_lo) == (-6.0, -(2.0 ** -59))
+    assert (odd.im_hi, odd.im_lo) == (1.0, 0.0)
+    even = B.perm_combine("real", 4, p + [B.Result(0.0, 0.0, 0.0, 0.0, None, terms=4, **kw)])
+    assert (even.re_hi, even.re_lo) == (6.0, 2.0 ** -59) and even.terms == 8
