@@ -164,6 +164,30 @@ perm_status perm_partial(int dtype, const void* dA, int n, int ld, uint64_t star
                          void* stream);
 
 /*
+ * perm_partial_noalloc -- perm_partial for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, ranges, result and errors as perm_partial,
+ * but the call allocates nothing (no hipMalloc, hipFree, pinned host memory or
+ * events): its staging copy, partial sums and result record live in a fixed
+ * array of device memory inside the library (370 KiB per device, held
+ * until the process ends), and the record is copied into `out` before the call
+ * returns (it waits for `stream`).  kernel_ms is 0 (no events); total_ms is the
+ * host wall time of the call.
+ *   Limit: each walk launch uses at most PERM_NOALLOC_MAX_BLOCKS workgroups
+ *   (0 = min(8 per CU, that limit), the same grid as perm_partial on a device of
+ *   at most 256 CUs, so the two give identical bits there); opts->blocks above
+ *   it is rejected with PERM_EINVAL.
+ *   All calls on one device share that array and it keeps the last call's
+ *   contents (each call writes every part it reads): calls that overlap on one
+ *   device (several host threads or streams) race, and the caller must
+ *   serialise them.  Calls on different devices are independent.
+ */
+#define PERM_NOALLOC_MAX_BLOCKS 2048
+perm_status perm_partial_noalloc(int dtype, const void* dA, int n, int ld, uint64_t start,
+                                 uint64_t count, const perm_opts* opts, perm_result* out,
+                                 void* stream);
+
+/*
  * perm_combine -- App. A, permanent: per(A) = 2 (-1)^n sum_k S_k from the
  * partial sums S_k of perm_partial over ranges that together cover
  * [0, 2^(n-1)) once (any cut into pieces, e.g. equal slices run one after

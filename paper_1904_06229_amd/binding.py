@@ -55,6 +55,8 @@ SIGNATURES = {
     "perm_int01": ([_vp, _i, _i, ctypes.POINTER(perm_opts), ctypes.POINTER(perm_result), _vp], _i),
     "perm_partial": ([_i, _vp, _i, _i, _u64, _u64, ctypes.POINTER(perm_opts),
                       ctypes.POINTER(perm_result), _vp], _i),
+    "perm_partial_noalloc": ([_i, _vp, _i, _i, _u64, _u64, ctypes.POINTER(perm_opts),
+                              ctypes.POINTER(perm_result), _vp], _i),
     "perm_batched": ([_vp, _vp, _vp, _i, _i, ctypes.POINTER(perm_opts), _vp, _vp, _vp], _i),
     "perm_sparse": ([_i, _vp, _i, _i, _i, _u64, ctypes.POINTER(perm_opts),
                      ctypes.POINTER(perm_result), _vp], _i),
@@ -224,13 +226,7 @@ def perm_int01(A, stream=None, **opts) -> Result:
     return _result(r, True)
 
 
-def perm_partial(A, start: int, count: int, stream=None, **opts) -> Result:
-    """Partial sum of the terms of A itself (entry A[i, j] in row i, column j).
-
-    Unlike the full permanent, a partial sum changes under transposition, so
-    the library must see A column-major: a row-major tensor is copied to
-    column-major storage first (pass A.t().contiguous().t() to avoid it).
-    """
+def _partial_call(fn, name, A, start, count, stream, opts) -> Result:
     import torch
     kind = {torch.float64: "real", torch.complex128: "complex", torch.uint8: "int01"}[A.dtype]
     dt = {"real": PERM_DT_REAL, "complex": PERM_DT_COMPLEX, "int01": PERM_DT_INT01}[kind]
@@ -238,9 +234,27 @@ def perm_partial(A, start: int, count: int, stream=None, **opts) -> Result:
         A = A.t().contiguous().t()
     p, n, ld = _matrix(A, kind)
     o, r = make_opts(**opts), perm_result()
-    _check(_lib.perm_partial(dt, p, n, ld, int(start), int(count), ctypes.byref(o),
-                             ctypes.byref(r), _stream_handle(stream)), "perm_partial")
+    _check(fn(dt, p, n, ld, int(start), int(count), ctypes.byref(o), ctypes.byref(r),
+              _stream_handle(stream)), name)
     return _result(r, kind == "int01")
+
+
+def perm_partial(A, start: int, count: int, stream=None, **opts) -> Result:
+    """Partial sum of the terms of A itself (entry A[i, j] in row i, column j).
+
+    Unlike the full permanent, a partial sum changes under transposition, so
+    the library must see A column-major: a row-major tensor is copied to
+    column-major storage first (pass A.t().contiguous().t() to avoid it).
+    """
+    return _partial_call(_lib.perm_partial, "perm_partial", A, start, count, stream, opts)
+
+
+def perm_partial_noalloc(A, start: int, count: int, stream=None, **opts) -> Result:
+    """perm_partial on the library's fixed device array (the library allocates
+    nothing; calls on one device must not overlap).  A column-major tensor
+    avoids the copy a row-major one gets here."""
+    return _partial_call(_lib.perm_partial_noalloc, "perm_partial_noalloc", A, start, count,
+                         stream, opts)
 
 
 def _to_struct(res: Result) -> perm_result:

@@ -41,6 +41,7 @@ SOURCES = [
     ("perm_batched.cpp", []),
     ("perm_mixed.cpp", []),
     ("perm_band.cpp", []),
+    ("perm_noalloc.hip", []),
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

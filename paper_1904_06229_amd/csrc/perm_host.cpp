@@ -47,18 +47,8 @@ struct Workspace {
   int device = -1;
   char* dmem = nullptr;
   DevResult* hres = nullptr;      // pinned host record
-  DevResult* hres_dev = nullptr;  // the same record as the device addresses it
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  int cu_count = 0;
-  // device sub-buffers
-  int32_t* status = nullptr;
-  int32_t* rowexp = nullptr;
-  double* bound = nullptr;
-  DevResult* dres = nullptr;
-  double* rowabs = nullptr;
-  double* staged = nullptr;
-  void* partials = nullptr;
-  double* drift = nullptr;
+  CallBuffers buf;                // device sub-buffers of dmem, the record, two events
 };
 
 // Workspaces are leased, one per call: a call takes an idle workspace of the
@@ -68,8 +58,6 @@ struct Workspace {
 std::mutex g_mu;
 std::map<int, std::vector<Workspace*>> g_idle;  // idle workspaces per device
 std::vector<Workspace*> g_all;                  // every workspace, for perm_release
-
-size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 void destroy_workspace(Workspace* w) {
   for (auto& ev : w->ev)
@@ -82,24 +70,7 @@ void destroy_workspace(Workspace* w) {
 perm_status create_workspace(int dev, Workspace** out) {
   Workspace* w = new Workspace();
   w->device = dev;
-  size_t off = 0;
-  const size_t o_status = off;
-  off = align_up(off + 64, 256);
-  const size_t o_rowexp = off;
-  off = align_up(off + sizeof(int32_t) * kMaxN, 256);
-  const size_t o_bound = off;
-  off = align_up(off + 64, 256);
-  const size_t o_res = off;
-  off = align_up(off + sizeof(DevResult), 256);
-  const size_t o_rowabs = off;
-  off = align_up(off + sizeof(double) * kMaxN, 256);
-  const size_t o_staged = off;
-  off = align_up(off + sizeof(double) * 4 * kMaxN * kMaxN, 256);
-  const size_t o_part = off;
-  off = align_up(off + sizeof(double) * 4 * (size_t)kMaxParts, 256);
-  const size_t o_drift = off;
-  off = align_up(off + sizeof(double) * (size_t)kMaxParts, 256);
-  hipError_t e = hipMalloc((void**)&w->dmem, off);
+  hipError_t e = hipMalloc((void**)&w->dmem, call_buffer_bytes(kMaxParts));
   if (e != hipSuccess) {
     w->dmem = nullptr;
     destroy_workspace(w);
@@ -111,9 +82,12 @@ perm_status create_workspace(int dev, Workspace** out) {
     destroy_workspace(w);
     return fail(PERM_ENOMEM, std::string("hipHostMalloc failed: ") + hipGetErrorString(e));
   }
+  CallBuffers& b = w->buf;
+  carve_call_buffers(w->dmem, kMaxParts, &b);
+  b.hres = w->hres;
   // The finishing kernel writes the result record straight into pinned host
   // memory (no separate copy); the stream synchronisation makes it visible.
-  e = hipHostGetDevicePointer((void**)&w->hres_dev, w->hres, 0);
+  e = hipHostGetDevicePointer((void**)&b.hres_dev, w->hres, 0);
   if (e != hipSuccess) {
     destroy_workspace(w);
     return fail(PERM_EHIP, std::string("hipHostGetDevicePointer failed: ") + hipGetErrorString(e));
@@ -126,18 +100,11 @@ perm_status create_workspace(int dev, Workspace** out) {
       return fail(PERM_EHIP, std::string("hipEventCreate failed: ") + hipGetErrorString(e));
     }
   }
+  b.ev_start = w->ev[1];
+  b.ev_stop = w->ev[2];
   hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, dev) == hipSuccess)
-    w->cu_count = prop.multiProcessorCount;
-  if (w->cu_count <= 0) w->cu_count = 256;
-  w->status = (int32_t*)(w->dmem + o_status);
-  w->rowexp = (int32_t*)(w->dmem + o_rowexp);
-  w->bound = (double*)(w->dmem + o_bound);
-  w->dres = (DevResult*)(w->dmem + o_res);
-  w->rowabs = (double*)(w->dmem + o_rowabs);
-  w->staged = (double*)(w->dmem + o_staged);
-  w->partials = (void*)(w->dmem + o_part);
-  w->drift = (double*)(w->dmem + o_drift);
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) b.cu_count = prop.multiProcessorCount;
+  if (b.cu_count <= 0) b.cu_count = 256;
   *out = w;
   return PERM_OK;
 }
@@ -163,18 +130,23 @@ perm_status acquire_workspace(Workspace** out) {
   return PERM_OK;
 }
 
-// A leased workspace.  It goes back to the idle list when the call returns;
-// if work was enqueued and the call is leaving early (an error after a
-// launch), the stream is drained first so that no kernel still uses it.
+// A leased workspace; it goes back to the idle list when the call returns.
 struct Lease {
   Workspace* w = nullptr;
-  hipStream_t s = nullptr;
-  bool pending = false;
   ~Lease() {
     if (!w) return;
-    if (pending) (void)hipStreamSynchronize(s);
     std::lock_guard<std::mutex> lk(g_mu);
     g_idle[w->device].push_back(w);
+  }
+};
+
+// If a call leaves early after enqueueing work (an error after a launch),
+// the stream is drained first so that no kernel still uses its buffers.
+struct Drain {
+  hipStream_t s = nullptr;
+  bool pending = false;
+  ~Drain() {
+    if (pending) (void)hipStreamSynchronize(s);
   }
 };
 
@@ -241,29 +213,26 @@ perm_status launch_walk(int kind, int n, int mode, bool drift, int variant, cons
   return PERM_OK;
 }
 
-// Stage, walk [start, start+count), finish, and bring the record back.
+// Stage, walk [start, start+count), finish, and bring the record back, on the
+// device buffers `bf`.
 // full: the range is the whole sum, so the 0/1 path may permute rows and
 // columns and use the pair-shared walk.
-perm_status run_range(int kind, const void* dA, int n, int ld, uint64_t start, uint64_t count,
-                      const perm_opts* opts, int range_check, bool full, hipStream_t s,
-                      Raw* raw) {
+perm_status run_range_on(const CallBuffers& bf, int kind, const void* dA, int n, int ld,
+                         uint64_t start, uint64_t count, const perm_opts* opts, int range_check,
+                         bool full, hipStream_t s, Raw* raw) {
   perm_opts o{};
   if (opts) o = *opts;
   const int is_int = kind == kInt01;
   perm_plan_info plan;
   perm_status st = perm_plan(n, start, count, o.log2_chunk, is_int, &plan);
   if (st != PERM_OK) return st;
-  Lease lease;
-  st = acquire_workspace(&lease.w);
-  if (st != PERM_OK) return st;
-  Workspace* ws = lease.w;
-  lease.s = s;
   // 8 workgroups (32 waves) per CU: more than can be resident, so the
   // dispatcher hands out the remaining workgroups as others finish, which
-  // evens out the tail.
-  const int cap = o.blocks > 0 ? o.blocks : 8 * ws->cu_count;
+  // evens out the tail.  Three launches (head, body, tail) fit the partials.
+  const int cap = std::min(o.blocks > 0 ? o.blocks : 8 * bf.cu_count, bf.max_parts / 3);
   const bool drift = o.drift_check != 0;
   const int mode = is_int ? 0 : o.precision;
+  const bool timed = bf.ev_start && bf.ev_stop;
 
   const int pair_rows = (is_int && full && !drift && plan.log2_chunk >= 1 &&
                          plan.head_count == 0 && plan.tail_count == 0 &&
@@ -273,35 +242,37 @@ perm_status run_range(int kind, const void* dA, int n, int ld, uint64_t start, u
   // Only the walk is timed with events (each record is a marker packet in the
   // stream, a few microseconds of gap); the whole call is timed on the host.
   const auto t_call = std::chrono::steady_clock::now();
-  lease.pending = true;
+  Drain drain;
+  drain.s = s;
+  drain.pending = true;
   HIP_TRY(launch_stage(kind, dA, n, ld, o.no_row_scaling ? 0 : 1, range_check, pair_rows,
-                       ws->staged, ws->rowabs, ws->rowexp, ws->status, ws->bound, s));
+                       bf.staged, bf.rowabs, bf.rowexp, bf.status, bf.bound, s));
 
   int nparts = 0;
   int body_grid = 0;
-  char* part_base = (char*)ws->partials;
+  char* part_base = (char*)bf.partials;
   const size_t part_bytes = (kind == kComplex) ? 32 : 16;
   auto walk = [&](uint64_t first, uint64_t nchunks, int b, int variant,
                   int* grid_out) -> perm_status {
     if (nchunks == 0) return PERM_OK;
     WalkArgs a;
-    a.staged = ws->staged;
-    a.rowabs = ws->rowabs;
-    a.status = ws->status;
+    a.staged = bf.staged;
+    a.rowabs = bf.rowabs;
+    a.status = bf.status;
     a.first = first;
     a.nchunks = nchunks;
     a.ntasks = 2 * ((nchunks + 2 * kWave - 1) / (2 * kWave));
     a.b = b;
     a.drift = drift ? 1 : 0;
     a.partials = part_base + part_bytes * nparts;
-    a.drift_part = ws->drift + nparts;
+    a.drift_part = bf.drift + nparts;
     const int grid = grid_for(a.ntasks, cap);
     if (grid_out) *grid_out = grid;
     nparts += grid;
     return launch_walk(kind, n, mode, drift, variant, a, grid, s);
   };
 
-  HIP_TRY(hipEventRecord(ws->ev[1], s));
+  if (timed) HIP_TRY(hipEventRecord(bf.ev_start, s));
   if ((st = walk(plan.head_start, plan.head_count, 0, 0, nullptr)) != PERM_OK) return st;
   // Pair-shared 0/1 walk: the walk kernel takes it when the staging kernel's
   // flag allows it, else walks plainly (one launch).
@@ -309,19 +280,36 @@ perm_status run_range(int kind, const void* dA, int n, int ld, uint64_t start, u
                  &body_grid)) != PERM_OK)
     return st;
   if ((st = walk(plan.tail_start, plan.tail_count, 0, 0, nullptr)) != PERM_OK) return st;
-  HIP_TRY(hipEventRecord(ws->ev[2], s));
-  HIP_TRY(launch_finish(kind, ws->partials, nparts, ws->drift, drift ? 1 : 0, ws->status,
-                        ws->rowexp, n, ws->bound, ws->hres_dev, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  lease.pending = false;
-  raw->r = *ws->hres;
+  if (timed) HIP_TRY(hipEventRecord(bf.ev_stop, s));
+  HIP_TRY(launch_finish(kind, bf.partials, nparts, bf.drift, drift ? 1 : 0, bf.status, bf.rowexp,
+                        n, bf.bound, bf.hres ? bf.hres_dev : bf.dres, s));
+  if (bf.hres) {
+    HIP_TRY(hipStreamSynchronize(s));
+    raw->r = *bf.hres;
+  } else {
+    // no pinned record: copy the device record into host memory
+    HIP_TRY(hipMemcpyAsync(&raw->r, bf.dres, sizeof(DevResult), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  drain.pending = false;
   raw->plan = plan;
   raw->blocks = body_grid;
   raw->kernel_ms = 0.0f;
-  (void)hipEventElapsedTime(&raw->kernel_ms, ws->ev[1], ws->ev[2]);
+  if (timed) (void)hipEventElapsedTime(&raw->kernel_ms, bf.ev_start, bf.ev_stop);
   raw->total_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() -
                                                           t_call).count();
   return PERM_OK;
+}
+
+// run_range_on with a leased workspace of the current device.
+perm_status run_range(int kind, const void* dA, int n, int ld, uint64_t start, uint64_t count,
+                      const perm_opts* opts, int range_check, bool full, hipStream_t s,
+                      Raw* raw) {
+  Lease lease;
+  perm_status st = acquire_workspace(&lease.w);
+  if (st != PERM_OK) return st;
+  return run_range_on(lease.w->buf, kind, dA, n, ld, start, count, opts, range_check, full, s,
+                      raw);
 }
 
 void fill_common(const Raw& raw, uint64_t count, perm_result* out) {
@@ -410,6 +398,52 @@ perm_status float_call(int kind, const double* dA, int n, int ld, const perm_opt
   r.im_hi = std::ldexp(f * raw.r.v[2], e);
   r.im_lo = std::ldexp(f * raw.r.v[3], e);
   fill_common(raw, T, &r);
+  *out = r;
+  return PERM_OK;
+}
+
+perm_status partial_impl(const CallBuffers* bf, int dtype, const void* dA, int n, int ld,
+                         uint64_t start, uint64_t count, const perm_opts* opts, perm_result* out,
+                         void* stream) {
+  if (!out) return fail(PERM_EINVAL, "out is NULL");
+  if (dtype < 0 || dtype > 2) return fail(PERM_EINVAL, "dtype must be 0, 1 or 2");
+  if (n < 1 || n > kMaxN) return fail(PERM_EINVAL, "n must be in [1, 64]");
+  if (ld < n) return fail(PERM_EINVAL, "ld must be >= n");
+  if (!dA) return fail(PERM_EINVAL, "dA is NULL");
+  const int kind = dtype == PERM_DT_REAL ? kReal : (dtype == PERM_DT_COMPLEX ? kComplex : kInt01);
+  perm_status st = check_opts(opts, kind == kInt01);
+  if (st != PERM_OK) return st;
+  if (bf && opts && opts->blocks > bf->max_parts / 3)
+    return fail(PERM_EINVAL, "blocks exceeds the " + std::to_string(bf->max_parts / 3) +
+                                 " workgroups the fixed device array holds partials for");
+  const uint64_t T = total_terms(n);
+  if (start > T || count > T - start) return fail(PERM_EINVAL, "range outside [0, 2^(n-1))");
+  perm_result r{};
+  r.max_drift = -1.0;
+  if (count == 0) {
+    *out = r;
+    return PERM_OK;
+  }
+  Raw raw;
+  st = bf ? run_range_on(*bf, kind, dA, n, ld, start, count, opts, 0, false, (hipStream_t)stream,
+                         &raw)
+          : run_range(kind, dA, n, ld, start, count, opts, 0, false, (hipStream_t)stream, &raw);
+  if (st != PERM_OK) return st;
+  st = status_from_device(raw.r.status);
+  if (st != PERM_OK) return st;
+  if (kind == kInt01) {
+    r.int_lo = raw.r.iw[0];
+    r.int_hi = (int64_t)raw.r.iw[1];
+    const __int128 v = (__int128)(((unsigned __int128)raw.r.iw[1] << 64) | raw.r.iw[0]);
+    pair_from_i128(v, &r.re_hi, &r.re_lo);
+  } else {
+    const int e = -raw.r.exp_sum;
+    r.re_hi = std::ldexp(raw.r.v[0], e);
+    r.re_lo = std::ldexp(raw.r.v[1], e);
+    r.im_hi = std::ldexp(raw.r.v[2], e);
+    r.im_lo = std::ldexp(raw.r.v[3], e);
+  }
+  fill_common(raw, count, &r);
   *out = r;
   return PERM_OK;
 }
@@ -508,42 +542,7 @@ perm_status perm_int01(const uint8_t* dA, int n, int ld, const perm_opts* opts, 
 
 perm_status perm_partial(int dtype, const void* dA, int n, int ld, uint64_t start, uint64_t count,
                          const perm_opts* opts, perm_result* out, void* stream) {
-  if (!out) return fail(PERM_EINVAL, "out is NULL");
-  if (dtype < 0 || dtype > 2) return fail(PERM_EINVAL, "dtype must be 0, 1 or 2");
-  if (n < 1 || n > kMaxN) return fail(PERM_EINVAL, "n must be in [1, 64]");
-  if (ld < n) return fail(PERM_EINVAL, "ld must be >= n");
-  if (!dA) return fail(PERM_EINVAL, "dA is NULL");
-  const int kind = dtype == PERM_DT_REAL ? kReal : (dtype == PERM_DT_COMPLEX ? kComplex : kInt01);
-  perm_status st = check_opts(opts, kind == kInt01);
-  if (st != PERM_OK) return st;
-  const uint64_t T = total_terms(n);
-  if (start > T || count > T - start) return fail(PERM_EINVAL, "range outside [0, 2^(n-1))");
-  perm_result r{};
-  r.max_drift = -1.0;
-  if (count == 0) {
-    *out = r;
-    return PERM_OK;
-  }
-  Raw raw;
-  st = run_range(kind, dA, n, ld, start, count, opts, 0, false, (hipStream_t)stream, &raw);
-  if (st != PERM_OK) return st;
-  st = status_from_device(raw.r.status);
-  if (st != PERM_OK) return st;
-  if (kind == kInt01) {
-    r.int_lo = raw.r.iw[0];
-    r.int_hi = (int64_t)raw.r.iw[1];
-    const __int128 v = (__int128)(((unsigned __int128)raw.r.iw[1] << 64) | raw.r.iw[0]);
-    pair_from_i128(v, &r.re_hi, &r.re_lo);
-  } else {
-    const int e = -raw.r.exp_sum;
-    r.re_hi = std::ldexp(raw.r.v[0], e);
-    r.re_lo = std::ldexp(raw.r.v[1], e);
-    r.im_hi = std::ldexp(raw.r.v[2], e);
-    r.im_lo = std::ldexp(raw.r.v[3], e);
-  }
-  fill_common(raw, count, &r);
-  *out = r;
-  return PERM_OK;
+  return partial_impl(nullptr, dtype, dA, n, ld, start, count, opts, out, stream);
 }
 
 perm_status perm_combine(int dtype, int n, const perm_result* parts, int count,
@@ -640,4 +639,10 @@ void perm_release(void) {
 
 namespace perm {
 perm_status set_error(perm_status s, const char* msg) { return fail(s, msg); }
+
+perm_status partial_on_buffers(const CallBuffers& bf, int dtype, const void* dA, int n, int ld,
+                               uint64_t start, uint64_t count, const perm_opts* opts,
+                               perm_result* out, void* stream) {
+  return partial_impl(&bf, dtype, dA, n, ld, start, count, opts, out, stream);
+}
 }  // namespace perm

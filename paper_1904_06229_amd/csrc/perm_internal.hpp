@@ -50,6 +50,56 @@ struct DevResult {
 
 enum Kind { kReal = 0, kComplex = 1, kInt01 = 2 };
 
+// Device buffers of one single-matrix call (stage, walks, finish), carved out
+// of one block of device memory; see carve_call_buffers for the layout.
+struct CallBuffers {
+  int32_t* status = nullptr;   // staging status words
+  int32_t* rowexp = nullptr;   // row-scaling exponents (kMaxN)
+  double* bound = nullptr;     // 0/1 path: log2 accumulator bound
+  DevResult* dres = nullptr;   // device result record
+  double* rowabs = nullptr;    // kMaxN row norms (drift normalisation)
+  double* staged = nullptr;    // +A then -A: 4 kMaxN^2 doubles (complex)
+  void* partials = nullptr;    // max_parts slots of 32 bytes
+  double* drift = nullptr;     // max_parts doubles
+  int max_parts = 0;
+  DevResult* hres = nullptr;      // pinned host record, or null: the record is copied back
+  DevResult* hres_dev = nullptr;  // hres as the device addresses it
+  hipEvent_t ev_start = nullptr;  // events around the walks, or null: no kernel timing
+  hipEvent_t ev_stop = nullptr;
+  int cu_count = 256;
+};
+
+constexpr size_t call_align(size_t x) { return (x + 255) / 256 * 256; }
+
+// Byte offsets of the sub-buffers; index 8 is the total size.
+constexpr size_t call_buffer_offset(int part, int max_parts) {
+  const size_t sz[8] = {64,
+                        sizeof(int32_t) * kMaxN,
+                        64,
+                        sizeof(DevResult),
+                        sizeof(double) * kMaxN,
+                        sizeof(double) * 4 * kMaxN * kMaxN,
+                        32 * (size_t)max_parts,
+                        sizeof(double) * (size_t)max_parts};
+  size_t off = 0;
+  for (int k = 0; k < part; ++k) off = call_align(off + sz[k]);
+  return off;
+}
+
+constexpr size_t call_buffer_bytes(int max_parts) { return call_buffer_offset(8, max_parts); }
+
+inline void carve_call_buffers(char* base, int max_parts, CallBuffers* b) {
+  b->status = (int32_t*)(base + call_buffer_offset(0, max_parts));
+  b->rowexp = (int32_t*)(base + call_buffer_offset(1, max_parts));
+  b->bound = (double*)(base + call_buffer_offset(2, max_parts));
+  b->dres = (DevResult*)(base + call_buffer_offset(3, max_parts));
+  b->rowabs = (double*)(base + call_buffer_offset(4, max_parts));
+  b->staged = (double*)(base + call_buffer_offset(5, max_parts));
+  b->partials = (void*)(base + call_buffer_offset(6, max_parts));
+  b->drift = (double*)(base + call_buffer_offset(7, max_parts));
+  b->max_parts = max_parts;
+}
+
 // Each walk family is built as two translation units (n <= 32 and n > 32);
 // the launch_walk_* dispatchers in perm_host.cpp pick one by n.
 hipError_t launch_walk_real_lo(int n, int mode, bool drift, const WalkArgs& a, int grid,

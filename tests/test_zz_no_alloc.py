@@ -1,0 +1,101 @@
+"""GPU: perm_partial_noalloc, the entry point that allocates nothing.
+
+It runs perm_partial's kernels on a fixed device array inside the library, so
+on the same input, range and grid it must give perm_partial's bits.  Two
+calls in a row per kind, the second with a smaller matrix (the array keeps
+the first call's contents, which the second must not read), each compared
+with perm_partial through the C-ABI and with the oracle's direct-term sum
+(App. A, subpermanent) at the FP64 bar (exactly for 0/1 input).
+"""
+import sys
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1904_06229_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def inp():
+    from paper_1904_06229_amd import inputs
+    return inputs
+
+
+def dev_cm(A):
+    return torch.from_numpy(np.asfortranarray(A)).to("cuda")
+
+
+def bits(r):
+    return (r.re_hi, r.re_lo, r.im_hi, r.im_lo, r.exact, r.terms, r.chunks, r.log2_chunk)
+
+
+def cval(x):
+    if hasattr(x, "re_hi"):
+        return (Fraction(x.re_hi) + Fraction(x.re_lo), Fraction(x.im_hi) + Fraction(x.im_lo))
+    if hasattr(x, "re"):
+        return (x.re.exact, x.im.exact)
+    return (x.exact, Fraction(0))
+
+
+def rel(got, want):
+    g, w = cval(got), cval(want)
+    num = (g[0] - w[0]) ** 2 + (g[1] - w[1]) ** 2
+    return float(num / (w[0] ** 2 + w[1] ** 2)) ** 0.5
+
+
+def matrix(inp, kind, n, seed):
+    if kind == "real":
+        return inp.real_gaussian(n, seed)
+    if kind == "complex":
+        return inp.complex_gaussian(n, seed, scale=n ** -0.5)
+    return inp.bernoulli01(n, seed)
+
+
+@pytest.mark.parametrize("kind", ["real", "complex", "int01"])
+def test_noalloc_matches_perm_partial_twice(B, orc, inp, kind):
+    # first call: 24 x 24, an unaligned range of 2^20 + 77 terms; second: 13 x 13, all terms
+    cases = [(24, 31, 12345, (1 << 20) + 77), (13, 32, 0, 1 << 12)]
+    for n, seed, start, count in cases:
+        A = matrix(inp, kind, n, seed)
+        dA = dev_cm(A)
+        got = B.perm_partial_noalloc(dA, start, count)
+        ref = B.perm_partial(dA, start, count)
+        print(f"  {kind} n={n} [{start}, +{count}): blocks {got.blocks} vs {ref.blocks}",
+              file=sys.stderr, flush=True)
+        assert got.terms == count
+        if got.blocks == ref.blocks:
+            assert bits(got) == bits(ref)
+        want = orc.chunk_partial(A, start, count)
+        if kind == "int01":
+            assert got.exact == ref.exact == want
+        else:
+            assert rel(got, ref) < TOL
+            assert rel(got, want) < TOL
+
+
+def test_noalloc_options_and_limits(B, inp):
+    A = inp.real_gaussian(18, 40)
+    dA = dev_cm(A)
+    a = B.perm_partial_noalloc(dA, 5, 9999, blocks=64, log2_chunk=4, precision="fp64")
+    b = B.perm_partial(dA, 5, 9999, blocks=64, log2_chunk=4, precision="fp64")
+    assert bits(a) == bits(b)
+    d = B.perm_partial_noalloc(dA, 0, 1 << 17, drift_check=1)
+    assert 0.0 <= d.max_drift < 1e-12
+    with pytest.raises(B.PermError) as e:
+        B.perm_partial_noalloc(dA, 0, 1 << 10, blocks=2049)
+    assert e.value.status == B.PERM_EINVAL
+    with pytest.raises(B.PermError) as e:
+        B.perm_partial_noalloc(dA, 1 << 16, 1 << 17)
+    assert e.value.status == B.PERM_EINVAL
+    # the entry point still works after the rejected calls
+    assert bits(B.perm_partial_noalloc(dA, 0, 1 << 17)) == bits(B.perm_partial(dA, 0, 1 << 17))
