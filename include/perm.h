@@ -92,12 +92,18 @@ typedef struct {
   uint64_t chunks;       /* lane chunks walked (including single-term ragged ends) */
   int32_t log2_chunk;    /* chunk length used */
   int32_t blocks;        /* workgroups of the main walk launch */
-  float kernel_ms;       /* duration of the walk launches, from HIP events on `stream` */
+  float kernel_ms;       /* duration of the walk launches, from HIP events on `stream`;
+                            on the one-launch path (walk_variant 1 of perm_real and
+                            perm_complex) the device wall clock from the first workgroup's
+                            start to the result */
   float total_ms;        /* perm_real, perm_complex, perm_int01, perm_partial: wall time of
                             the call on the host, from entry until the result is in host
                             memory.  perm_repeated*, perm_sparse*: HIP events on `stream`
                             from staging to the result */
-  int32_t walk_variant;  /* perm_int01: 1 if the pair-shared walk ran, else 0.  perm_sparse
+  int32_t walk_variant;  /* perm_int01: 1 if the pair-shared walk ran, else 0.  perm_real,
+                            perm_complex: 1 if the one-launch path ran (n <= 24 with
+                            default blocks and no drift check: staging, walk and the
+                            fixed-order sum in one kernel), else 0.  perm_sparse
                             with PERM_DT_INT01: the row groups of the exact product (1..4),
                             or 0 for the size-only grouping.  Otherwise 0 */
   int32_t col0_nonzeros; /* 0/1 path, pair-shared walk: ones in the column flipped between the

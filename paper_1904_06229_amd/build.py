@@ -36,6 +36,7 @@ SOURCES = [
     ("kern_mixed_stage.hip", []),
     ("kern_band.hip", []),
     ("kern_stage.hip", []),
+    ("kern_fused.hip", []),
     ("kern_batched.hip", []),
     ("perm_host.cpp", []),
     ("perm_batched.cpp", []),

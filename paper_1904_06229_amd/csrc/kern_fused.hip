@@ -1,0 +1,259 @@
+// One-launch permanent of a small real or complex matrix (App. A,
+// subpermanent and permanent over the whole range [0, 2^(n-1))).
+//
+// For small n the walk itself takes a few microseconds, and the separate
+// staging and finishing launches (with the gaps between dependent launches)
+// would cost more than it.  Here one launch does all three steps:
+//
+//   1. every workgroup stages its own copy of the matrix: the entries go to
+//      LDS, each row gets its power-of-two scale (as stage_float_kernel:
+//      row 2-norm in [2, 4), exact, undone by the host), and +A / -A are
+//      written to the workgroup's own slot of device memory, from where the
+//      walk reads its columns with scalar loads.  The slot is written and
+//      read by this workgroup only; the stores are waited for before the
+//      barrier, so the scalar loads (which go to L2) find them;
+//   2. the waves walk their chunks exactly as walk_real_kernel /
+//      walk_complex_kernel do (same lane -> chunk map, same pair loop);
+//   3. each workgroup writes its double-double partial, and the workgroup
+//      that finishes last (a device-wide completion counter) adds all
+//      partials in workgroup order along the same fixed tree as
+//      finish_kernel, writes the result record and sets the counter back to
+//      zero for the next call.  The order of the sum does not depend on
+//      which workgroup finishes last, so results are bit-reproducible.
+//      The record also carries the launch's duration in wall-clock ticks:
+//      from the earliest workgroup start (an atomic minimum) to the end.
+//
+// MODE 0: FP64 products, double-double lane sums (default)
+// MODE 1: FP64 products, plain FP64 lane sums
+// MODE 2: FP32 products of the FP64 row sums, double-double lane sums
+#include "perm_walk.hpp"
+
+namespace perm {
+namespace {
+
+// Threads that share one row in the row statistics (a power of two that
+// divides the wave, kFusedMaxN * kRowThreads <= kBlock).
+constexpr int kRowThreads = 8;
+static_assert(kFusedMaxN * kRowThreads <= kBlock, "row statistics need a thread group per row");
+
+template <int N, bool CPLX>
+__device__ __forceinline__ void fused_stage(const FusedArgs& a, double* slot, int32_t* s_exp,
+                                            int32_t* s_bad, double* s_a) {
+  constexpr int CW = CPLX ? 2 : 1;
+  constexpr int TOT = CW * N * N;
+  constexpr int LOADS = (TOT + kBlock - 1) / kBlock;
+  const int tid = threadIdx.x;
+  {
+    double v[LOADS];
+#pragma unroll
+    for (int u = 0; u < LOADS; ++u) {
+      const int t = tid + u * kBlock;
+      const int idx = t / CW, c = t - CW * (t / CW);
+      const int i = idx % N, j = idx / N;
+      v[u] = t < TOT ? a.A[CW * ((size_t)i + (size_t)j * a.ld) + c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < LOADS; ++u) {
+      const int t = tid + u * kBlock;
+      if (t < TOT) s_a[t] = v[u];
+    }
+  }
+  __syncthreads();
+  // row statistics: kRowThreads threads per row, each over every
+  // kRowThreads-th column, combined by shuffles inside the group (fixed order)
+  {
+    const int i = tid / kRowThreads, sub = tid % kRowThreads;
+    double mx = 0.0;
+    int bad = 0;
+    if (i < N) {
+      for (int j = sub; j < N; j += kRowThreads)
+#pragma unroll
+        for (int c = 0; c < CW; ++c) {
+          const double x = s_a[CW * (i + j * N) + c];
+          bad |= !isfinite(x);
+          mx = fmax(mx, fabs(x));
+        }
+    }
+#pragma unroll
+    for (int off = 1; off < kRowThreads; off <<= 1) {
+      mx = fmax(mx, __shfl_xor(mx, off));
+      bad |= __shfl_xor(bad, off);
+    }
+    double ss = 0.0;
+    if (i < N && !bad && mx > 0.0) {
+      for (int j = sub; j < N; j += kRowThreads)
+#pragma unroll
+        for (int c = 0; c < CW; ++c) {
+          const double x = s_a[CW * (i + j * N) + c] / mx;
+          ss += x * x;
+        }
+    }
+#pragma unroll
+    for (int off = 1; off < kRowThreads; off <<= 1) ss += __shfl_xor(ss, off);
+    if (i < N && sub == 0) {
+      int e = 0;
+      if (!bad && a.row_scaling && mx > 0.0) {
+        // norm = mx sqrt(ss) in [2^(k-1), 2^k): exponents taken apart so a row
+        // near the top of the double range does not overflow the product
+        int k1, k2;
+        const double f = frexp(mx, &k1) * frexp(sqrt(ss), &k2);  // in [1/4, 1)
+        int k = k1 + k2;
+        if (f < 0.5) --k;
+        e = 2 - k;
+        e = e < -1000 ? -1000 : (e > 1000 ? 1000 : e);
+      }
+      s_exp[i] = e;
+      if (bad) atomicOr(s_bad, 1);
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < TOT; t += kBlock) {
+    const int i = (t / CW) % N;
+    const double v = ldexp(s_a[t], s_exp[i]);
+    slot[t] = v;
+    slot[TOT + t] = -v;
+  }
+  // The walk reads the slot with scalar loads, which go to L2: wait until
+  // this thread's stores have completed there, then meet the other waves.
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+}
+
+template <int N, bool CPLX, int MODE>
+__global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs a) {
+  constexpr int CW = CPLX ? 2 : 1;
+  __shared__ double s_a[CW * N * N];
+  __shared__ int32_t s_exp[N];
+  __shared__ int32_t s_bad;
+  __shared__ int32_t s_last;
+  __shared__ dd s_re[kBlock], s_im[kBlock];
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_bad = 0;
+    atomicMin((unsigned long long*)a.t0, (unsigned long long)wall_clock64());
+  }
+  double* slot = a.slots + (size_t)blockIdx.x * a.slot_stride;
+  fused_stage<N, CPLX>(a, slot, s_exp, &s_bad, s_a);
+  const bool ok = s_bad == 0;
+
+  const int lane = tid & (kWave - 1);
+  const uint64_t wave = wave_id();
+  const uint64_t nwaves = (uint64_t)gridDim.x * kWavesPerBlock;
+  dd re{0.0, 0.0}, im{0.0, 0.0};
+  double dr = 0.0;  // no drift check on this path
+  if (ok) {
+    for (uint64_t task = wave; task < a.ntasks; task += nwaves) {
+      const uint64_t c = task_chunk(task, lane);
+      const uint32_t gpar = (uint32_t)(task & 1);
+      if constexpr (CPLX) {
+        const cdd part = walk_chunk_complex<N, MODE, false>(slot, nullptr, c, a.b, gpar, dr);
+        if (c < a.nchunks) {
+          re = dd_add(re, part.re);
+          im = dd_add(im, part.im);
+        }
+      } else {
+        const dd part = walk_chunk_real<N, MODE, false>(slot, nullptr, c, a.b, gpar, dr);
+        if (c < a.nchunks) re = dd_add(re, part);
+      }
+    }
+  }
+  // this workgroup's partial (as the walk kernels)
+  const dd vr = wave_sum(re);
+  const dd br = block_sum(vr, dd_add);
+  dd bi{0.0, 0.0};
+  if constexpr (CPLX) {
+    const dd vi = wave_sum(im);
+    __syncthreads();
+    bi = block_sum(vi, dd_add);
+  }
+  if (tid == 0) {
+    double* p = a.partials + 4 * (size_t)blockIdx.x;
+    p[0] = br.hi;
+    p[1] = br.lo;
+    p[2] = bi.hi;
+    p[3] = bi.lo;
+    __threadfence();  // the partial is visible device-wide before it is counted
+    const uint32_t done = atomicAdd(a.counter, 1u);
+    s_last = done == gridDim.x - 1 ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  // The last workgroup: every other partial has been counted, so it is visible.
+  __threadfence();
+  const int nparts = (int)gridDim.x;
+  re = dd{0.0, 0.0};
+  im = dd{0.0, 0.0};
+  for (int k = tid; k < nparts; k += kBlock) {
+    const double* p = a.partials + 4 * (size_t)k;
+    re = dd_add(re, dd{p[0], p[1]});
+    im = dd_add(im, dd{p[2], p[3]});
+  }
+  s_re[tid] = re;
+  s_im[tid] = im;
+  __syncthreads();
+  for (int stride = kBlock / 2; stride > 0; stride >>= 1) {
+    if (tid < stride) {
+      s_re[tid] = dd_add(s_re[tid], s_re[tid + stride]);
+      s_im[tid] = dd_add(s_im[tid], s_im[tid + stride]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    int32_t es = 0;
+    for (int i = 0; i < N; ++i) es += s_exp[i];
+    DevResult* r = a.res;
+    r->v[0] = s_re[0].hi;
+    r->v[1] = s_re[0].lo;
+    r->v[2] = s_im[0].hi;
+    r->v[3] = s_im[0].lo;
+    r->iw[0] = 0;
+    r->iw[1] = 0;
+    r->drift = -1.0;
+    r->status = ok ? kStOk : kStNonFinite;
+    r->exp_sum = es;
+    r->bound = 0.0;
+    r->variant = 1;  // reported as walk_variant: the one-launch path ran
+    r->ones0 = 0;
+    const unsigned long long start = atomicExch((unsigned long long*)a.t0, ~0ull);
+    r->ticks = (uint64_t)wall_clock64() - (uint64_t)start;
+    atomicExch(a.counter, 0u);  // ready for the next call on these buffers
+  }
+}
+
+template <int N, bool CPLX>
+hipError_t dispatch(int mode, const FusedArgs& a, int grid, hipStream_t s) {
+  const dim3 g(grid), blk(kBlock);
+  switch (mode) {
+    case 0: hipLaunchKernelGGL((fused_kernel<N, CPLX, 0>), g, blk, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((fused_kernel<N, CPLX, 1>), g, blk, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((fused_kernel<N, CPLX, 2>), g, blk, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t dispatch_n(bool cplx, int mode, const FusedArgs& a, int grid, hipStream_t s) {
+  return cplx ? dispatch<N, true>(mode, a, grid, s) : dispatch<N, false>(mode, a, grid, s);
+}
+
+}  // namespace
+
+hipError_t launch_fused(bool cplx, int n, int mode, const FusedArgs& a, int grid, hipStream_t s) {
+  switch (n) {
+#define PERM_FUSED_CASE(N) \
+  case N:                  \
+    return dispatch_n<N>(cplx, mode, a, grid, s);
+    PERM_FUSED_CASE(2) PERM_FUSED_CASE(3) PERM_FUSED_CASE(4) PERM_FUSED_CASE(5)
+    PERM_FUSED_CASE(6) PERM_FUSED_CASE(7) PERM_FUSED_CASE(8) PERM_FUSED_CASE(9)
+    PERM_FUSED_CASE(10) PERM_FUSED_CASE(11) PERM_FUSED_CASE(12) PERM_FUSED_CASE(13)
+    PERM_FUSED_CASE(14) PERM_FUSED_CASE(15) PERM_FUSED_CASE(16) PERM_FUSED_CASE(17)
+    PERM_FUSED_CASE(18) PERM_FUSED_CASE(19) PERM_FUSED_CASE(20) PERM_FUSED_CASE(21)
+    PERM_FUSED_CASE(22) PERM_FUSED_CASE(23) PERM_FUSED_CASE(24)
+#undef PERM_FUSED_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace perm

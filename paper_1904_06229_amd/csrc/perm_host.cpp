@@ -46,10 +46,13 @@ constexpr int kInt01ChunkCap = 10;
 struct Workspace {
   int device = -1;
   char* dmem = nullptr;
+  char* fmem = nullptr;           // one-launch path: workgroup slots, counter, start time
   DevResult* hres = nullptr;      // pinned host record
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   CallBuffers buf;                // device sub-buffers of dmem, the record, two events
 };
+
+constexpr size_t kFusedSlotBytes = sizeof(double) * (size_t)kFusedMaxBlocks * kFusedSlotDoubles;
 
 // Workspaces are leased, one per call: a call takes an idle workspace of the
 // current device (or allocates one) and gives it back when it returns, after
@@ -64,6 +67,7 @@ void destroy_workspace(Workspace* w) {
     if (ev) (void)hipEventDestroy(ev);
   if (w->hres) (void)hipHostFree(w->hres);
   if (w->dmem) (void)hipFree(w->dmem);
+  if (w->fmem) (void)hipFree(w->fmem);
   delete w;
 }
 
@@ -82,8 +86,26 @@ perm_status create_workspace(int dev, Workspace** out) {
     destroy_workspace(w);
     return fail(PERM_ENOMEM, std::string("hipHostMalloc failed: ") + hipGetErrorString(e));
   }
+  e = hipMalloc((void**)&w->fmem, kFusedSlotBytes + 256);
+  if (e != hipSuccess) {
+    w->fmem = nullptr;
+    destroy_workspace(w);
+    return fail(PERM_ENOMEM, std::string("hipMalloc of workspace failed: ") + hipGetErrorString(e));
+  }
   CallBuffers& b = w->buf;
   carve_call_buffers(w->dmem, kMaxParts, &b);
+  b.fused_slots = (double*)w->fmem;
+  b.counter = (uint32_t*)(w->fmem + kFusedSlotBytes);
+  b.t0 = (uint64_t*)(w->fmem + kFusedSlotBytes + 8);
+  // counter 0, start time all ones (set once; every launch leaves them so)
+  e = hipMemset(b.counter, 0, 8);
+  if (e == hipSuccess) e = hipMemset(b.t0, 0xff, 8);
+  if (e != hipSuccess) {
+    destroy_workspace(w);
+    return fail(PERM_EHIP, std::string("hipMemset failed: ") + hipGetErrorString(e));
+  }
+  if (hipDeviceGetAttribute(&b.wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
+    b.wall_khz = 0;
   b.hres = w->hres;
   // The finishing kernel writes the result record straight into pinned host
   // memory (no separate copy); the stream synchronisation makes it visible.
@@ -213,6 +235,55 @@ perm_status launch_walk(int kind, int n, int mode, bool drift, int variant, cons
   return PERM_OK;
 }
 
+// The whole sum of a small real or complex matrix in one launch (stage, walk
+// and the fixed-order finish in kern_fused.hip), when the buffers have the
+// workgroup slots and the options ask for nothing that launch lacks.
+bool fused_eligible(const CallBuffers& bf, int kind, int n, const perm_opts& o,
+                    const perm_plan_info& plan) {
+  return bf.fused_slots && kind != kInt01 && n >= 2 && n <= kFusedMaxN && !o.drift_check &&
+         o.blocks == 0 && plan.log2_chunk >= 1 && plan.head_count == 0 && plan.tail_count == 0;
+}
+
+perm_status run_fused_on(const CallBuffers& bf, int kind, const void* dA, int n, int ld,
+                         const perm_opts& o, const perm_plan_info& plan, hipStream_t s, Raw* raw) {
+  const auto t_call = std::chrono::steady_clock::now();
+  FusedArgs a;
+  a.A = (const double*)dA;
+  a.ld = ld;
+  a.row_scaling = o.no_row_scaling ? 0 : 1;
+  a.slots = bf.fused_slots;
+  const uint64_t cw = kind == kComplex ? 2 : 1;
+  a.slot_stride = (2 * cw * n * n + 31) / 32 * 32;  // 256-byte aligned slots
+  a.ntasks = plan.body_tasks;
+  a.nchunks = plan.body_chunks;
+  a.b = plan.log2_chunk;
+  a.pad = 0;
+  a.partials = (double*)bf.partials;
+  a.counter = bf.counter;
+  a.t0 = bf.t0;
+  a.res = bf.hres ? bf.hres_dev : bf.dres;
+  const int grid = grid_for(plan.body_tasks, std::min(8 * bf.cu_count, kFusedMaxBlocks));
+  Drain drain;
+  drain.s = s;
+  drain.pending = true;
+  hipError_t e = launch_fused(kind == kComplex, n, o.precision, a, grid, s);
+  if (e != hipSuccess) return fail(PERM_EHIP, std::string("fused launch failed: ") + hipGetErrorString(e));
+  if (bf.hres) {
+    HIP_TRY(hipStreamSynchronize(s));
+    raw->r = *bf.hres;
+  } else {
+    HIP_TRY(hipMemcpyAsync(&raw->r, bf.dres, sizeof(DevResult), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  drain.pending = false;
+  raw->plan = plan;
+  raw->blocks = grid;
+  raw->kernel_ms = bf.wall_khz > 0 ? (float)((double)raw->r.ticks / bf.wall_khz) : 0.0f;
+  raw->total_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() -
+                                                          t_call).count();
+  return PERM_OK;
+}
+
 // Stage, walk [start, start+count), finish, and bring the record back, on the
 // device buffers `bf`.
 // full: the range is the whole sum, so the 0/1 path may permute rows and
@@ -226,6 +297,8 @@ perm_status run_range_on(const CallBuffers& bf, int kind, const void* dA, int n,
   perm_plan_info plan;
   perm_status st = perm_plan(n, start, count, o.log2_chunk, is_int, &plan);
   if (st != PERM_OK) return st;
+  if (full && fused_eligible(bf, kind, n, o, plan))
+    return run_fused_on(bf, kind, dA, n, ld, o, plan, s, raw);
   // 8 workgroups (32 waves) per CU: more than can be resident, so the
   // dispatcher hands out the remaining workgroups as others finish, which
   // evens out the tail.  Three launches (head, body, tail) fit the partials.

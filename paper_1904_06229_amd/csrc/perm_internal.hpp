@@ -46,6 +46,8 @@ struct DevResult {
   double bound;       // 0/1 path: log2 accumulator bound
   int32_t variant;    // 0/1 path: 1 if the pair-shared walk ran
   int32_t ones0;      // 0/1 path: ones in the staged column 0
+  uint64_t ticks;     // one-launch path: wall-clock ticks from the first workgroup's
+                      // start to the result (0 elsewhere)
 };
 
 enum Kind { kReal = 0, kComplex = 1, kInt01 = 2 };
@@ -67,6 +69,11 @@ struct CallBuffers {
   hipEvent_t ev_start = nullptr;  // events around the walks, or null: no kernel timing
   hipEvent_t ev_stop = nullptr;
   int cu_count = 256;
+  // one-launch path (small real and complex permanents); null: not available
+  double* fused_slots = nullptr;  // kFusedMaxBlocks slots of kFusedSlotDoubles
+  uint32_t* counter = nullptr;    // finished workgroups; zero between calls
+  uint64_t* t0 = nullptr;         // earliest workgroup start; all ones between calls
+  int wall_khz = 0;               // rate of the device wall clock
 };
 
 constexpr size_t call_align(size_t x) { return (x + 255) / 256 * 256; }
@@ -119,6 +126,31 @@ hipError_t launch_walk_int01_hi(int n, bool drift, int variant, const WalkArgs& 
 // the device, in one launch).
 // Smallest pair_rows (n/3) for which the pair-shared 0/1 walk is built.
 constexpr int kInt01PairMinRows = 3;
+
+// One-launch permanent of a small real or complex matrix: every workgroup
+// stages its own copy, walks its chunks, and the last one to finish adds the
+// partials in workgroup order (kern_fused.hip).
+constexpr int kFusedMaxN = 24;
+constexpr int kFusedMaxBlocks = 512;
+constexpr int kFusedSlotDoubles = 2 * 2 * kFusedMaxN * kFusedMaxN;  // +A, -A, complex
+
+struct FusedArgs {
+  const double* A;        // caller's matrix, column-major, leading dimension ld
+  int32_t ld;
+  int32_t row_scaling;
+  double* slots;          // per workgroup: its staged +A then -A (ld = n)
+  uint64_t slot_stride;   // doubles between workgroup slots
+  uint64_t ntasks;        // wave tasks of the aligned chunks of [0, 2^(n-1))
+  uint64_t nchunks;
+  int32_t b;              // log2 chunk length (>= 1)
+  int32_t pad;
+  double* partials;       // 4 doubles per workgroup
+  uint32_t* counter;      // zero on entry; set back to zero by the last workgroup
+  uint64_t* t0;           // all ones on entry; set back by the last workgroup
+  DevResult* res;         // result record
+};
+
+hipError_t launch_fused(bool cplx, int n, int mode, const FusedArgs& a, int grid, hipStream_t s);
 
 // Staging: validate A, choose row exponents, write +A/-A (0/1: +2A/-2A).
 // 0/1 input with pair_rows > 0: the matrix is permuted (sparsest column
