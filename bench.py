@@ -142,7 +142,11 @@ def parse():
                    help="untimed steps first (default 3; c3, c4, c6, c8: 1; 0 for a whole "
                         "sliced permanent)")
     p.add_argument("--workload", default="c3",
-                   choices=["c1", "c2", "c3", "c4", "c5", "c6", "c7", "c8", "c9"])
+                   choices=["c1", "c2", "c3", "c4", "c5", "c6", "c7", "c8", "c9", "dense"])
+    p.add_argument("--n", type=int, default=48,
+                   help="dense: matrix size (2..64)")
+    p.add_argument("--kind", default="complex", choices=["complex", "real"],
+                   help="dense: complex Ginibre/sqrt(n) or real N(0,1) entries")
     p.add_argument("--count", type=int, default=100000, help="c4: number of matrices")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-autotune", action="store_true",
@@ -181,11 +185,19 @@ def parse():
         args.warmup = warmup
     if args.steps < 1 or args.warmup < 0:
         p.error("--steps must be >= 1 and --warmup >= 0")
+    if args.workload == "dense" and not 2 <= args.n <= 64:
+        p.error("--n must be in 2..64")
     return args
 
 
-def make_workload(name):
+def make_workload(name, args=None):
     from paper_1904_06229_amd import inputs
+    if name == "dense":
+        n, seed = args.n, 20190400 + args.n
+        if args.kind == "complex":
+            return "complex", n, inputs.complex_gaussian(n, seed, scale=n ** -0.5), \
+                f"{n}x{n} complex128 Ginibre/sqrt(n), seed {seed}"
+        return "real", n, inputs.real_gaussian(n, seed), f"{n}x{n} real N(0,1), seed {seed}"
     if name == "c1":
         n = 20
         return "complex", n, inputs.complex_gaussian(n, 20190401, scale=n ** -0.5), \
@@ -719,7 +731,7 @@ def bench_sliced(args):
     import torch
     from paper_1904_06229_amd import longrun
 
-    kind, n, A, desc = make_workload(args.workload)
+    kind, n, A, desc = make_workload(args.workload, args)
     dA = torch.from_numpy(np.asfortranarray(A)).to("cuda")
     slices = args.slices or 16
     kw = dict(blocks=args.blocks, log2_chunk=args.log2_chunk)
@@ -833,7 +845,7 @@ def main():
 
     if args.calibrate_copy:
         calibrate_copy()
-    kind, n, A, desc = make_workload(args.workload)
+    kind, n, A, desc = make_workload(args.workload, args)
     dA = torch.from_numpy(np.ascontiguousarray(A)).to("cuda")
     fn = {"int01": B.perm_int01, "real": B.perm_real, "complex": B.perm_complex}[kind]
     kw = dict(blocks=args.blocks, log2_chunk=args.log2_chunk)

@@ -31,6 +31,18 @@ __device__ __forceinline__ const double* opaque(const double* p) {
   return p;
 }
 
+// The (uniform) pointer p, released only once v has been computed.  A column
+// of a large complex matrix is more data than the scalar registers hold, so
+// its reads are split into blocks, and each block's reads are tied to the
+// update of an earlier block: the loads in flight then never exceed what the
+// SGPRs hold (otherwise the compiler issues them all at once and spills the
+// SGPRs into VGPR lanes, which costs VALU instructions in the walk).  The
+// empty asm emits no instruction.
+__device__ __forceinline__ const double* after(const double* p, double v) {
+  asm volatile("" : "+s"(p) : "v"(v));
+  return p;
+}
+
 // ---------------------------------------------------------------- gray ----
 
 __device__ __forceinline__ uint64_t gray(uint64_t k) { return k ^ (k >> 1); }

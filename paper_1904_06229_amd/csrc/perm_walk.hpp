@@ -103,14 +103,34 @@ __device__ __forceinline__ void term_prod_complex(const double (&wr)[N], const d
     prod_c64<N>(wr, wi, pr, pi);
 }
 
+// Sizes above this read a complex column in blocks of kColRows rows, block k
+// only after block k-2 has been added (at most two blocks, 64 SGPRs, in flight).
+constexpr int kColBlockedFrom = 49;
+constexpr int kColRows = 8;
+
 template <int N>
 __device__ __forceinline__ void add_col_complex(double (&wr)[N], double (&wi)[N],
                                         const double* __restrict__ staged, uint32_t sub, int j) {
-  cdptr col = as_const(staged + sub * (2 * N * N) + 2 * j * N);
+  const double* base = staged + sub * (2 * N * N) + 2 * j * N;
+  if constexpr (N < kColBlockedFrom) {
+    cdptr col = as_const(base);
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    wr[i] += col[2 * i];
-    wi[i] += col[2 * i + 1];
+    for (int i = 0; i < N; ++i) {
+      wr[i] += col[2 * i];
+      wi[i] += col[2 * i + 1];
+    }
+  } else {
+#pragma unroll
+    for (int r0 = 0; r0 < N; r0 += kColRows) {
+      const double* p = base + 2 * r0;
+      if (r0 >= 2 * kColRows) p = after(p, wi[r0 - kColRows - 1]);
+      cdptr col = as_const(p);
+#pragma unroll
+      for (int i = r0; i < r0 + kColRows && i < N; ++i) {
+        wr[i] += col[2 * (i - r0)];
+        wi[i] += col[2 * (i - r0) + 1];
+      }
+    }
   }
 }
 

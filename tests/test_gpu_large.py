@@ -139,3 +139,18 @@ def test_split_precision_reported_error(B, orc, inp):
         sp = rel(val(B.perm_complex(dev_cm(A), precision="split")), want)
         log(f"  n={n}: FP64 {dd:.2e}  FP32-product {sp:.2e}")
         assert dd < TOL and sp < 1e-3
+
+
+@pytest.mark.parametrize("n", [49, 56, 57, 63])
+def test_large_complex_blocked_column_reads(B, orc, inp, n):
+    """Complex n >= 49 reads each column in blocks of 8 rows (the last block
+    shorter when 8 does not divide n): aligned chunks of 2^12 terms at the start,
+    the end and inside the range against the oracle's direct terms, with the
+    chunk-end drift check."""
+    L = 1 << 12
+    A = inp.complex_gaussian(n, 4900 + n, scale=n ** -0.5)
+    picks = sampled_chunks(n, L, 6, n)
+    worst = check_chunks(B, orc, A, n, L, "dd", TOL, picks)
+    r = B.perm_partial(dev_cm(A), picks[2] * L, 64 * L, log2_chunk=12, drift_check=True)
+    assert 0.0 <= r.max_drift < 1e-12
+    log(f"  complex n={n}: 6 chunks of 2^12, worst rel err {worst:.2e}, drift {r.max_drift:.1e}")
