@@ -78,7 +78,23 @@ typedef struct {
   int32_t blocks;         /* workgroups of the walk kernel; 0 = automatic (8 per CU) */
   int32_t use_graph;      /* perm_batched: replay a captured HIP graph when the same
                              arguments come again (1) or launch directly (0) */
-  int32_t reserved[2];    /* must be 0 */
+  int32_t partials_cap;   /* records available at partials_out (0 when it is NULL) */
+  int32_t reserved;       /* must be 0 */
+  double* partials_out;   /* optional DEVICE array (perm_real, perm_complex, perm_int01,
+                             perm_partial, perm_partial_noalloc): the partial sums the
+                             final sum is taken over -- one record per workgroup of the
+                             walk launches, in the order they are added (the paper keeps
+                             such an array before its final compensated sum, Sec. II.B).
+                             Record k = 5 doubles: re_hi, re_lo, im_hi, im_lo of the
+                             workgroup's double-double sum of its terms (in the sign
+                             convention of perm_partial, scaled back to A itself; 0/1
+                             input: words 0 and 1 hold the low and high 64 bits of its
+                             two's-complement 128-bit integer sum of prod_i 2w_i, words 2
+                             and 3 are 0), then the largest row-sum drift of its chunks
+                             (drift_check; -1 otherwise).  perm_result.parts = the number
+                             of records.  Too small a partials_cap is PERM_EINVAL.  The
+                             array is filled on `stream` before the call returns.  Other
+                             entry points reject it (PERM_ENOTIMPL) */
 } perm_opts;
 
 /* Result of a single-matrix call. */
@@ -108,6 +124,9 @@ typedef struct {
                             or 0 for the size-only grouping.  Otherwise 0 */
   int32_t col0_nonzeros; /* 0/1 path, pair-shared walk: ones in the column flipped between the
                             two terms of every pair; otherwise 0 */
+  int32_t parts;         /* partial sums the result was added from (the records written
+                            to opts->partials_out when it is given) */
+  int32_t pad;
 } perm_result;
 
 /*

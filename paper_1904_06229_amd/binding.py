@@ -26,7 +26,8 @@ class perm_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("log2_chunk", ctypes.c_int32),
                 ("drift_check", ctypes.c_int32), ("no_row_scaling", ctypes.c_int32),
                 ("blocks", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("partials_cap", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("partials_out", ctypes.c_void_p)]
 
 
 class perm_result(ctypes.Structure):
@@ -37,7 +38,8 @@ class perm_result(ctypes.Structure):
                 ("chunks", ctypes.c_uint64), ("log2_chunk", ctypes.c_int32),
                 ("blocks", ctypes.c_int32), ("kernel_ms", ctypes.c_float),
                 ("total_ms", ctypes.c_float), ("walk_variant", ctypes.c_int32),
-                ("col0_nonzeros", ctypes.c_int32)]
+                ("col0_nonzeros", ctypes.c_int32), ("parts", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 class perm_plan_info(ctypes.Structure):
@@ -122,6 +124,7 @@ class Result:
     total_ms: float
     walk_variant: int = 0
     col0_nonzeros: int = 0
+    parts: int = 0
 
     @property
     def value(self):
@@ -139,11 +142,13 @@ def _result(r: perm_result, exact: bool) -> Result:
         ex = v - (1 << 128) if v >= (1 << 127) else v
     return Result(r.re_hi, r.re_lo, r.im_hi, r.im_lo, ex, r.max_drift, r.terms, r.chunks,
                   r.log2_chunk, r.blocks, r.kernel_ms, r.total_ms, r.walk_variant,
-                  r.col0_nonzeros)
+                  r.col0_nonzeros, r.parts)
 
 
 def make_opts(precision="dd", log2_chunk=0, drift_check=False, row_scaling=True, blocks=0,
-              use_graph=False) -> perm_opts:
+              use_graph=False, partials=None) -> perm_opts:
+    """partials: an optional float64 device tensor for the partial-sum records
+    (5 doubles each; its size sets partials_cap)."""
     o = perm_opts()
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.log2_chunk = int(log2_chunk)
@@ -151,6 +156,13 @@ def make_opts(precision="dd", log2_chunk=0, drift_check=False, row_scaling=True,
     o.no_row_scaling = 0 if row_scaling else 1
     o.blocks = int(blocks)
     o.use_graph = 1 if use_graph else 0
+    if partials is not None:
+        import torch
+        if partials.dtype != torch.float64 or not partials.is_contiguous() \
+                or partials.device.type != "cuda":
+            raise TypeError("partials must be a contiguous float64 device tensor")
+        o.partials_out = partials.data_ptr()
+        o.partials_cap = min(partials.numel() // 5, 2 ** 31 - 1)
     return o
 
 

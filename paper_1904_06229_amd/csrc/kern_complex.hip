@@ -51,7 +51,9 @@ __global__ __launch_bounds__(kBlock) void walk_complex_kernel(WalkArgs a) {
     out[4 * blockIdx.x + 2] = bi.hi;
     out[4 * blockIdx.x + 3] = bi.lo;
   }
-  if (DRIFT) {
+  // drift-checked calls: every launch writes its slot (the single-term launches
+  // of unaligned range ends, which cannot drift, write 0)
+  if (DRIFT || a.drift) {
     __syncthreads();
     const double m = wave_max(drift);
     const double bm = block_sum(m, [](double x, double y) { return fmax(x, y); });

@@ -197,7 +197,9 @@ __global__ __launch_bounds__(kBlock) void walk_int01_kernel(WalkArgs a) {
     out[2 * blockIdx.x] = blk.lo;
     out[2 * blockIdx.x + 1] = blk.hi;
   }
-  if (DRIFT) {
+  // drift-checked calls: every launch writes its slot (the single-term launches
+  // of unaligned range ends, which cannot drift, write 0)
+  if (DRIFT || a.drift) {
     const double m = wave_max(drift);
     const double bm = block_sum(m, [](double x, double y) { return fmax(x, y); });
     if (threadIdx.x == 0) a.drift_part[blockIdx.x] = bm;

@@ -325,7 +325,55 @@ __global__ __launch_bounds__(kBlock) void finish_kernel(const void* __restrict__
   }
 }
 
+// The per-workgroup partials as caller records of 5 doubles (re hi, re lo,
+// im hi, im lo, drift), scaled back to the unscaled matrix (2^-sum e_i,
+// exact); 0/1 partials as their two 64-bit words.
+__global__ __launch_bounds__(kBlock) void export_partials_kernel(
+    int kind, const void* __restrict__ partials, const double* __restrict__ drift_part,
+    int want_drift, int nparts, const int32_t* __restrict__ rowexp, int n, double* out) {
+  __shared__ int32_t s_es;
+  if (threadIdx.x == 0) {
+    int32_t es = 0;
+    for (int i = 0; i < n; ++i) es += rowexp[i];
+    s_es = es;
+  }
+  __syncthreads();
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= nparts) return;
+  double* o = out + 5 * (size_t)k;
+  const int e = -s_es;
+  if (kind == kInt01) {
+    const uint64_t* p = (const uint64_t*)partials;
+    o[0] = __longlong_as_double((long long)p[2 * k]);
+    o[1] = __longlong_as_double((long long)p[2 * k + 1]);
+    o[2] = 0.0;
+    o[3] = 0.0;
+  } else if (kind == kComplex) {
+    const double* p = (const double*)partials;
+    o[0] = ldexp(p[4 * k], e);
+    o[1] = ldexp(p[4 * k + 1], e);
+    o[2] = ldexp(p[4 * k + 2], e);
+    o[3] = ldexp(p[4 * k + 3], e);
+  } else {
+    const double* p = (const double*)partials;
+    o[0] = ldexp(p[2 * k], e);
+    o[1] = ldexp(p[2 * k + 1], e);
+    o[2] = 0.0;
+    o[3] = 0.0;
+  }
+  o[4] = want_drift ? drift_part[k] : -1.0;
+}
+
 }  // namespace
+
+hipError_t launch_export_partials(int kind, const void* partials, const double* drift_part,
+                                  int want_drift, int nparts, const int32_t* rowexp, int n,
+                                  double* out, hipStream_t s) {
+  if (nparts <= 0) return hipSuccess;
+  hipLaunchKernelGGL(export_partials_kernel, dim3((nparts + kBlock - 1) / kBlock), dim3(kBlock),
+                     0, s, kind, partials, drift_part, want_drift, nparts, rowexp, n, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_stage(int kind, const void* A, int n, int ld, int row_scaling, int range_check,
                         int pair_rows, double* staged, double* rowabs, int32_t* rowexp,

@@ -129,7 +129,8 @@ extern "C" perm_status perm_band(int dtype, const double* dA, const int32_t* h_n
   if (o.precision != PERM_FP64_DD || o.log2_chunk || o.drift_check || o.use_graph)
     return set_error(PERM_ENOTIMPL, "perm_band takes only the blocks option");
   if (o.blocks < 0 || o.blocks > 65536) return set_error(PERM_EINVAL, "blocks out of range");
-  if (o.reserved[0] || o.reserved[1]) return set_error(PERM_EINVAL, "reserved options must be 0");
+  if (o.reserved) return set_error(PERM_EINVAL, "reserved options must be 0");
+  if (o.partials_out) return set_error(PERM_ENOTIMPL, "partials_out is not provided here");
   for (int m = 0; m < count; ++m) {
     if (h_n[m] < 1 || h_n[m] > kBandMaxN) return set_error(PERM_EINVAL, "n must be in [1, 65536]");
     if (h_offset[m] < 0) return set_error(PERM_EINVAL, "offsets must be >= 0");

@@ -346,7 +346,8 @@ perm_status perm_batched(const double* dA, const int32_t* h_n, const int64_t* h_
     return set_error(PERM_ENOTIMPL, "perm_batched supports PERM_FP64_DD and PERM_FP64");
   if (o.log2_chunk < 0 || o.log2_chunk > 24) return set_error(PERM_EINVAL, "log2_chunk out of range");
   if (o.drift_check) return set_error(PERM_ENOTIMPL, "perm_batched has no drift check");
-  if (o.reserved[0] || o.reserved[1]) return set_error(PERM_EINVAL, "reserved options must be 0");
+  if (o.reserved) return set_error(PERM_EINVAL, "reserved options must be 0");
+  if (o.partials_out) return set_error(PERM_ENOTIMPL, "partials_out is not provided here");
   for (int m = 0; m < count; ++m) {
     if (h_n[m] < 1 || h_n[m] > kMaxBatchedN) return set_error(PERM_EINVAL, "batched n must be in [1, 32]");
     if (h_offset[m] < 0) return set_error(PERM_EINVAL, "negative offset");

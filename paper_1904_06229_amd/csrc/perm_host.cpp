@@ -205,7 +205,8 @@ perm_status check_opts(const perm_opts* o, int is_int01) {
     return fail(PERM_EINVAL, "log2_chunk out of range (max " + std::to_string(cap) + ")");
   if (o->blocks < 0 || o->blocks > kMaxParts / 3) return fail(PERM_EINVAL, "blocks out of range");
   if (o->drift_check < 0 || o->drift_check > 1) return fail(PERM_EINVAL, "drift_check must be 0 or 1");
-  if (o->reserved[0] || o->reserved[1]) return fail(PERM_EINVAL, "reserved options must be 0");
+  if (o->reserved) return fail(PERM_EINVAL, "reserved options must be 0");
+  if (o->partials_out && o->partials_cap < 0) return fail(PERM_EINVAL, "partials_cap must be >= 0");
   return PERM_OK;
 }
 
@@ -216,6 +217,7 @@ struct Raw {
   perm_plan_info plan;
   float kernel_ms, total_ms;
   int blocks;
+  int parts;  // partial sums added by the finish
 };
 
 perm_status launch_walk(int kind, int n, int mode, bool drift, int variant, const WalkArgs& a,
@@ -241,7 +243,8 @@ perm_status launch_walk(int kind, int n, int mode, bool drift, int variant, cons
 bool fused_eligible(const CallBuffers& bf, int kind, int n, const perm_opts& o,
                     const perm_plan_info& plan) {
   return bf.fused_slots && kind != kInt01 && n >= 2 && n <= kFusedMaxN && !o.drift_check &&
-         o.blocks == 0 && plan.log2_chunk >= 1 && plan.head_count == 0 && plan.tail_count == 0;
+         o.blocks == 0 && !o.partials_out && plan.log2_chunk >= 1 && plan.head_count == 0 &&
+         plan.tail_count == 0;
 }
 
 perm_status run_fused_on(const CallBuffers& bf, int kind, const void* dA, int n, int ld,
@@ -278,6 +281,7 @@ perm_status run_fused_on(const CallBuffers& bf, int kind, const void* dA, int n,
   drain.pending = false;
   raw->plan = plan;
   raw->blocks = grid;
+  raw->parts = grid;
   raw->kernel_ms = bf.wall_khz > 0 ? (float)((double)raw->r.ticks / bf.wall_khz) : 0.0f;
   raw->total_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() -
                                                           t_call).count();
@@ -312,6 +316,15 @@ perm_status run_range_on(const CallBuffers& bf, int kind, const void* dA, int n,
                          n / 3 >= kInt01PairMinRows)
                             ? n / 3
                             : 0;
+  // The partial-sum slots the three walk launches will fill (checked against
+  // the caller's records before anything is enqueued).
+  auto tasks_of = [](uint64_t nchunks) { return 2 * ((nchunks + 2 * kWave - 1) / (2 * kWave)); };
+  const int total_parts = (plan.head_count ? grid_for(tasks_of(plan.head_count), cap) : 0) +
+                          (plan.body_chunks ? grid_for(tasks_of(plan.body_chunks), cap) : 0) +
+                          (plan.tail_count ? grid_for(tasks_of(plan.tail_count), cap) : 0);
+  if (o.partials_out && total_parts > o.partials_cap)
+    return fail(PERM_EINVAL, "partials_out holds " + std::to_string(o.partials_cap) +
+                                 " records, the call needs " + std::to_string(total_parts));
   // Only the walk is timed with events (each record is a marker packet in the
   // stream, a few microseconds of gap); the whole call is timed on the host.
   const auto t_call = std::chrono::steady_clock::now();
@@ -356,6 +369,9 @@ perm_status run_range_on(const CallBuffers& bf, int kind, const void* dA, int n,
   if (timed) HIP_TRY(hipEventRecord(bf.ev_stop, s));
   HIP_TRY(launch_finish(kind, bf.partials, nparts, bf.drift, drift ? 1 : 0, bf.status, bf.rowexp,
                         n, bf.bound, bf.hres ? bf.hres_dev : bf.dres, s));
+  if (o.partials_out)
+    HIP_TRY(launch_export_partials(kind, bf.partials, bf.drift, drift ? 1 : 0, nparts, bf.rowexp,
+                                   n, o.partials_out, s));
   if (bf.hres) {
     HIP_TRY(hipStreamSynchronize(s));
     raw->r = *bf.hres;
@@ -367,6 +383,7 @@ perm_status run_range_on(const CallBuffers& bf, int kind, const void* dA, int n,
   drain.pending = false;
   raw->plan = plan;
   raw->blocks = body_grid;
+  raw->parts = nparts;
   raw->kernel_ms = 0.0f;
   if (timed) (void)hipEventElapsedTime(&raw->kernel_ms, bf.ev_start, bf.ev_stop);
   raw->total_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() -
@@ -395,6 +412,7 @@ void fill_common(const Raw& raw, uint64_t count, perm_result* out) {
   out->total_ms = raw.total_ms;
   out->walk_variant = raw.r.variant;
   out->col0_nonzeros = raw.r.variant ? raw.r.ones0 : 0;
+  out->parts = raw.parts;
 }
 
 perm_status status_from_device(int32_t st) {
@@ -626,12 +644,14 @@ perm_status perm_combine(int dtype, int n, const perm_result* parts, int count,
   if (count < 1) return fail(PERM_EINVAL, "count must be >= 1");
   const uint64_t T = total_terms(n);
   uint64_t terms = 0, chunks = 0;
+  int64_t nparts = 0;
   double drift = -1.0;
   float kms = 0.0f, tms = 0.0f;
   for (int k = 0; k < count; ++k) {
     if (parts[k].terms > T - terms) return fail(PERM_EINVAL, "the parts hold more than 2^(n-1) terms");
     terms += parts[k].terms;
     chunks += parts[k].chunks;
+    nparts += parts[k].parts;
     drift = std::max(drift, parts[k].max_drift);
     kms += parts[k].kernel_ms;
     tms += parts[k].total_ms;
@@ -645,6 +665,7 @@ perm_status perm_combine(int dtype, int n, const perm_result* parts, int count,
   r.total_ms = tms;
   r.log2_chunk = parts[0].log2_chunk;
   r.blocks = parts[0].blocks;
+  r.parts = (int32_t)std::min<int64_t>(nparts, INT32_MAX);
   if (dtype == PERM_DT_INT01) {
     // The parts hold sum (-1)^(g+1) prod_i r_i = (-1)^n 2^(n-1) per(A), mod 2^128.
     unsigned __int128 u = 0;

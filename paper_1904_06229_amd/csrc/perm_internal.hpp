@@ -160,6 +160,11 @@ hipError_t launch_stage(int kind, const void* A, int n, int ld, int row_scaling,
                         int pair_rows, double* staged, double* rowabs, int32_t* rowexp,
                         int32_t* status, double* bound, hipStream_t s);
 
+// The per-workgroup partials as the caller's records (perm_opts.partials_out).
+hipError_t launch_export_partials(int kind, const void* partials, const double* drift_part,
+                                  int want_drift, int nparts, const int32_t* rowexp, int n,
+                                  double* out, hipStream_t s);
+
 // Fixed-order sum of the per-workgroup partials into a DevResult.
 hipError_t launch_finish(int kind, const void* partials, int nparts, const double* drift_part,
                          int want_drift, const int32_t* status, const int32_t* rowexp, int n,

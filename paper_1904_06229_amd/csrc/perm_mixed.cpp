@@ -197,7 +197,8 @@ perm_status check_opts(const perm_opts& o) {
   if (o.log2_chunk < 0 || o.log2_chunk > kMixMaxLog2Chunk)
     return set_error(PERM_EINVAL, "log2_chunk out of range (max 14)");
   if (o.blocks < 0 || o.blocks > kMaxGrid) return set_error(PERM_EINVAL, "blocks out of range");
-  if (o.reserved[0] || o.reserved[1]) return set_error(PERM_EINVAL, "reserved options must be 0");
+  if (o.reserved) return set_error(PERM_EINVAL, "reserved options must be 0");
+  if (o.partials_out) return set_error(PERM_ENOTIMPL, "partials_out is not provided here");
   return PERM_OK;
 }
 

@@ -125,3 +125,31 @@ def test_size_offset_arrays_checked(b):
         b._host_ints([1.5], "int32")
     with pytest.raises(ValueError):
         b._host_ints([[1, 2]], "int64")
+
+
+def test_struct_layouts_match_the_header(b, tmp_path):
+    """The binding's ctypes structs have the C layout of perm.h (sizes and
+    field offsets from a small C program built against the header)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"perm_opts": b.perm_opts, "perm_result": b.perm_result,
+               "perm_plan_info": b.perm_plan_info}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "perm.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        name, field, value = line.split()
+        cls = structs[name]
+        want = ctypes.sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert int(value) == want, line
