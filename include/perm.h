@@ -19,8 +19,11 @@
  *     interleaved (re, im) doubles: a(i,j) = A[2(i+j*ld)] + i A[2(i+j*ld)+1].
  *     Since per(A) = per(A^T), a row-major caller may pass its array as is.
  *   - `stream` is a hipStream_t (NULL = the default stream).  All work is
- *     enqueued on it.  Single-matrix calls wait for that stream and return a
- *     host value; perm_batched only enqueues and returns at once.
+ *     enqueued on it.  Single-matrix calls return a host value once the result
+ *     is complete: they wait for that stream, or, on the one-launch path of
+ *     small real and complex permanents, for the result record the kernel
+ *     writes into pinned host memory as its last act; perm_batched only
+ *     enqueues and returns at once.
  *   - No pointer is kept after a call returns.  Library-owned device
  *     workspace (staged matrix, partial sums, item plans) is allocated lazily per
  *     device and kept until perm_release().

@@ -217,6 +217,9 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs a) {
     const unsigned long long start = atomicExch((unsigned long long*)a.t0, ~0ull);
     r->ticks = (uint64_t)wall_clock64() - (uint64_t)start;
     atomicExch(a.counter, 0u);  // ready for the next call on these buffers
+    // the record is complete (and visible to the host) before the flag
+    __threadfence_system();
+    *(volatile uint32_t*)&r->done = 1u;
   }
 }
 

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -237,6 +238,17 @@ perm_status launch_walk(int kind, int n, int mode, bool drift, int variant, cons
   return PERM_OK;
 }
 
+// Automatic chunk length of the one-launch path.  Every workgroup stages its
+// own copy, so fewer, longer-walking workgroups pay off there: measured on
+// one MI355X (host time per call, complex; real alike), the best lengths were
+// 2^2 at n = 16 (23.8 us), 2^4 at n = 20 (31.0 us, against 32.3 at 2^3),
+// 2^5 at n = 22 (41.6 us) and 2^7 at n = 24 (75.6 us).
+int fused_log2_chunk(int n) {
+  const int lg = n - 1;
+  const int b = lg <= 19 ? lg - 15 : lg - 16;
+  return std::min(lg, std::max(2, b));
+}
+
 // The whole sum of a small real or complex matrix in one launch (stage, walk
 // and the fixed-order finish in kern_fused.hip), when the buffers have the
 // workgroup slots and the options ask for nothing that launch lacks.
@@ -269,10 +281,24 @@ perm_status run_fused_on(const CallBuffers& bf, int kind, const void* dA, int n,
   Drain drain;
   drain.s = s;
   drain.pending = true;
+  volatile uint32_t* done = bf.hres ? &bf.hres->done : nullptr;
+  if (done) {
+    *done = 0u;
+    std::atomic_thread_fence(std::memory_order_seq_cst);
+  }
   hipError_t e = launch_fused(kind == kComplex, n, o.precision, a, grid, s);
   if (e != hipSuccess) return fail(PERM_EHIP, std::string("fused launch failed: ") + hipGetErrorString(e));
-  if (bf.hres) {
-    HIP_TRY(hipStreamSynchronize(s));
+  if (done) {
+    // The kernel writes the record into pinned host memory and sets `done`
+    // last: watching the flag returns as soon as the result is there, without
+    // the stream synchronisation's wake-up.  The stream is queried now and
+    // then, so an error (or a launch that never ran) ends the wait too.
+    for (uint32_t spin = 1; *done == 0u; ++spin) {
+      if ((spin & 1023u) == 0u && hipStreamQuery(s) != hipErrorNotReady) break;
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    if (*done == 0u) HIP_TRY(hipStreamSynchronize(s));
+    if (*done == 0u) return fail(PERM_EHIP, "one-launch kernel ended without its result");
     raw->r = *bf.hres;
   } else {
     HIP_TRY(hipMemcpyAsync(&raw->r, bf.dres, sizeof(DevResult), hipMemcpyDeviceToHost, s));
@@ -301,8 +327,15 @@ perm_status run_range_on(const CallBuffers& bf, int kind, const void* dA, int n,
   perm_plan_info plan;
   perm_status st = perm_plan(n, start, count, o.log2_chunk, is_int, &plan);
   if (st != PERM_OK) return st;
-  if (full && fused_eligible(bf, kind, n, o, plan))
+  if (full && fused_eligible(bf, kind, n, o, plan)) {
+    perm_plan_info fplan = plan;
+    if (o.log2_chunk == 0 &&
+        perm_plan(n, start, count, fused_log2_chunk(n), is_int, &fplan) != PERM_OK)
+      fplan = plan;
+    if (fused_eligible(bf, kind, n, o, fplan))
+      return run_fused_on(bf, kind, dA, n, ld, o, fplan, s, raw);
     return run_fused_on(bf, kind, dA, n, ld, o, plan, s, raw);
+  }
   // 8 workgroups (32 waves) per CU: more than can be resident, so the
   // dispatcher hands out the remaining workgroups as others finish, which
   // evens out the tail.  Three launches (head, body, tail) fit the partials.

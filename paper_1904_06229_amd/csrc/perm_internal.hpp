@@ -48,6 +48,8 @@ struct DevResult {
   int32_t ones0;      // 0/1 path: ones in the staged column 0
   uint64_t ticks;     // one-launch path: wall-clock ticks from the first workgroup's
                       // start to the result (0 elsewhere)
+  uint32_t done;      // one-launch path: set to 1 after every other field is written
+  uint32_t pad;
 };
 
 enum Kind { kReal = 0, kComplex = 1, kInt01 = 2 };
