@@ -265,7 +265,9 @@ perm_status perm_batched(const double* dA, const int32_t* h_n, const int64_t* h_
 /*
  * perm_autotune -- time candidate chunk lengths for the batched path on
  * synthetic matrices of each size in [n_lo, n_hi] (1 <= n_lo <= n_hi <= 32) and
- * keep the fastest per size for later perm_batched calls.  If cache_path is not
+ * keep the fastest per size for later perm_batched calls.  A chunk length 2^b
+ * fixes the lanes per matrix: 2^(n-1-b) lanes, one chunk each, in wave items of
+ * 64; the cache file lists both.  If cache_path is not
  * NULL the table is also written there as JSON (and perm_batched reads it back
  * when PERM_AUTOTUNE_CACHE names that file).  Waits for `stream`.
  */

@@ -288,6 +288,18 @@ void write_cache(const char* path) {
       }
     std::fprintf(f, "}");
   }
+  // the same choice as lanes per matrix: 2^(n-1-b) lane chunks of 2^b terms
+  for (int c = 0; c < 2; ++c) {
+    std::fprintf(f, ", \"lanes_%s\": {", names[c]);
+    bool first = true;
+    for (int n = 1; n <= kMaxBatchedN; ++n)
+      if (g_tune.b[c][n] >= 0) {
+        std::fprintf(f, "%s\"%d\": %llu", first ? "" : ", ", n,
+                     (unsigned long long)(1ull << (n - 1 - g_tune.b[c][n])));
+        first = false;
+      }
+    std::fprintf(f, "}");
+  }
   std::fprintf(f, "}\n");
   std::fclose(f);
 }
