@@ -848,8 +848,9 @@ def main():
     kind, n, A, desc = make_workload(args.workload, args)
     dA = torch.from_numpy(np.ascontiguousarray(A)).to("cuda")
     fn = {"int01": B.perm_int01, "real": B.perm_real, "complex": B.perm_complex}[kind]
-    kw = dict(blocks=args.blocks, log2_chunk=args.log2_chunk)
-    if kind != "int01":
+    # only the options that differ from the library's defaults (a plain call otherwise)
+    kw = {k: v for k, v in (("blocks", args.blocks), ("log2_chunk", args.log2_chunk)) if v}
+    if kind != "int01" and args.precision != "dd":
         kw["precision"] = args.precision
     terms = 2 ** (n - 1)
     if args.terms_log2:

@@ -172,12 +172,21 @@ def _stream_handle(stream):
     so that tensors produced there -- the caller's, or a column-major copy
     made here -- are complete before the library reads them."""
     import torch
-    cur = torch.cuda.current_stream()
     if stream is None:
-        return ctypes.c_void_p(cur.cuda_stream)
+        # torch's current stream as a raw handle, without building a Stream object
+        raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+        if raw is not None:
+            return ctypes.c_void_p(raw(torch.cuda.current_device()))
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    cur = torch.cuda.current_stream()
     if stream != cur:
         stream.wait_stream(cur)
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _opts_arg(opts):
+    """A perm_opts for the given keyword options, or None (NULL: the defaults)."""
+    return ctypes.byref(make_opts(**opts)) if opts else None
 
 
 def _matrix(A, dtype_name):
@@ -216,24 +225,24 @@ def _check(st, where):
 
 def perm_real(A, stream=None, **opts) -> Result:
     p, n, ld = _matrix(A, "real")
-    o, r = make_opts(**opts), perm_result()
-    _check(_lib.perm_real(p, n, ld, ctypes.byref(o), ctypes.byref(r), _stream_handle(stream)),
+    r = perm_result()
+    _check(_lib.perm_real(p, n, ld, _opts_arg(opts), ctypes.byref(r), _stream_handle(stream)),
            "perm_real")
     return _result(r, False)
 
 
 def perm_complex(A, stream=None, **opts) -> Result:
     p, n, ld = _matrix(A, "complex")
-    o, r = make_opts(**opts), perm_result()
-    _check(_lib.perm_complex(p, n, ld, ctypes.byref(o), ctypes.byref(r), _stream_handle(stream)),
+    r = perm_result()
+    _check(_lib.perm_complex(p, n, ld, _opts_arg(opts), ctypes.byref(r), _stream_handle(stream)),
            "perm_complex")
     return _result(r, False)
 
 
 def perm_int01(A, stream=None, **opts) -> Result:
     p, n, ld = _matrix(A, "int01")
-    o, r = make_opts(**opts), perm_result()
-    _check(_lib.perm_int01(p, n, ld, ctypes.byref(o), ctypes.byref(r), _stream_handle(stream)),
+    r = perm_result()
+    _check(_lib.perm_int01(p, n, ld, _opts_arg(opts), ctypes.byref(r), _stream_handle(stream)),
            "perm_int01")
     return _result(r, True)
 
