@@ -88,6 +88,13 @@ def _load():
         raise ImportError(
             f"{LIB_PATH} is missing: build it first (python -m paper_1904_06229_amd.build, "
             "or __graft_entry__.build()); there is no non-GPU fallback")
+    # torch first: the library must bind to the HIP runtime torch has loaded
+    # (torch ships its own copy; loaded the other way round, the process would
+    # hold two runtimes and the library's would see no device)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     for name, (args, res) in SIGNATURES.items():
         f = getattr(lib, name)
