@@ -153,3 +153,18 @@ def test_struct_layouts_match_the_header(b, tmp_path):
         cls = structs[name]
         want = ctypes.sizeof(cls) if field == "size" else getattr(cls, field).offset
         assert int(value) == want, line
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """Importing the binding before torch must not load a second HIP runtime
+    (torch ships its own libamdhip64; the library has to use that one)."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1904_06229_amd import binding\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], check=True, capture_output=True,
+                         text=True).stdout.strip().splitlines()[-1]
+    assert out == "1"
