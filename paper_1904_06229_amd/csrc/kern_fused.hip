@@ -16,9 +16,9 @@
 //      walk_complex_kernel do (same lane -> chunk map, same pair loop);
 //   3. each workgroup writes its double-double partial, and the workgroup
 //      that finishes last (a device-wide completion counter) adds all
-//      partials in workgroup order along the same fixed tree as
-//      finish_kernel, writes the result record and sets the counter back to
-//      zero for the next call.  The order of the sum does not depend on
+//      partials in a fixed order (one wave: strided lane sums, then the
+//      shuffle butterfly), writes the result record and sets the counter back
+//      to zero for the next call.  The order of the sum does not depend on
 //      which workgroup finishes last, so results are bit-reproducible.
 //      The record also carries the launch's duration in wall-clock ticks:
 //      from the earliest workgroup start (an atomic minimum) to the end.
@@ -126,7 +126,6 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs a) {
   __shared__ int32_t s_exp[N];
   __shared__ int32_t s_bad;
   __shared__ int32_t s_last;
-  __shared__ dd s_re[kBlock], s_im[kBlock];
   const int tid = threadIdx.x;
   if (tid == 0) {
     s_bad = 0;
@@ -179,33 +178,28 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs a) {
   __syncthreads();
   if (!s_last) return;
   // The last workgroup: every other partial has been counted, so it is visible.
+  // Its first wave adds them -- lane l takes partials l, l + 64, ... in order,
+  // then the lanes meet along the shuffle butterfly -- with no barrier.
   __threadfence();
+  if (tid >= kWave) return;
   const int nparts = (int)gridDim.x;
   re = dd{0.0, 0.0};
   im = dd{0.0, 0.0};
-  for (int k = tid; k < nparts; k += kBlock) {
+  for (int k = tid; k < nparts; k += kWave) {
     const double* p = a.partials + 4 * (size_t)k;
     re = dd_add(re, dd{p[0], p[1]});
     im = dd_add(im, dd{p[2], p[3]});
   }
-  s_re[tid] = re;
-  s_im[tid] = im;
-  __syncthreads();
-  for (int stride = kBlock / 2; stride > 0; stride >>= 1) {
-    if (tid < stride) {
-      s_re[tid] = dd_add(s_re[tid], s_re[tid + stride]);
-      s_im[tid] = dd_add(s_im[tid], s_im[tid + stride]);
-    }
-    __syncthreads();
-  }
+  re = wave_sum(re);
+  im = wave_sum(im);
   if (tid == 0) {
     int32_t es = 0;
     for (int i = 0; i < N; ++i) es += s_exp[i];
     DevResult* r = a.res;
-    r->v[0] = s_re[0].hi;
-    r->v[1] = s_re[0].lo;
-    r->v[2] = s_im[0].hi;
-    r->v[3] = s_im[0].lo;
+    r->v[0] = re.hi;
+    r->v[1] = re.lo;
+    r->v[2] = im.hi;
+    r->v[3] = im.lo;
     r->iw[0] = 0;
     r->iw[1] = 0;
     r->drift = -1.0;
