@@ -15,13 +15,25 @@
 namespace perm {
 namespace {
 
+// Sizes from kSplitFrom on keep rows [R, n) of the row sums in LDS (the
+// plain chunk walk; drift-checked and single-term launches keep every row in
+// registers) and run two waves per SIMD.
+template <int N, bool DRIFT, bool SINGLE>
+constexpr bool split_rows() {
+  return N >= kSplitFrom && !DRIFT && !SINGLE;
+}
+
 template <int N, int MODE, bool DRIFT, bool SINGLE>
-__global__ __launch_bounds__(kBlock) void walk_complex_kernel(WalkArgs a) {
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(split_rows<N, DRIFT, SINGLE>() ? 2 : 1)))
+void walk_complex_kernel(WalkArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint64_t wave = wave_id();
   const uint64_t nwaves = (uint64_t)gridDim.x * kWavesPerBlock;
   dd re{0.0, 0.0}, im{0.0, 0.0};
   double drift = 0.0;
+  double2* rows = nullptr;
+  if constexpr (split_rows<N, DRIFT, SINGLE>()) rows = lane_rows<SplitRows<N>::L>();
   if (a.status[0] == kStOk) {
     for (uint64_t task = wave; task < a.ntasks; task += nwaves) {
       const uint64_t c = task_chunk(task, lane);
@@ -30,6 +42,8 @@ __global__ __launch_bounds__(kBlock) void walk_complex_kernel(WalkArgs a) {
       cdd part;
       if constexpr (SINGLE)
         part = single_term_complex<N, MODE>(a.staged, a.first + c);
+      else if constexpr (split_rows<N, DRIFT, SINGLE>())
+        part = walk_chunk_complex_split<N, MODE>(a.staged, a.first + c, a.b, gpar, rows);
       else
         part = walk_chunk_complex<N, MODE, DRIFT>(a.staged, a.rowabs, a.first + c, a.b, gpar, dr);
       if (c < a.nchunks) {

@@ -103,30 +103,33 @@ __device__ __forceinline__ void term_prod_complex(const double (&wr)[N], const d
     prod_c64<N>(wr, wi, pr, pi);
 }
 
-// Sizes above this read a complex column in blocks of kColRows rows, block k
-// only after block k-2 has been added (at most two blocks, 64 SGPRs, in flight).
+// Columns of this many rows or more are read in blocks of kColRows rows,
+// block k only after block k-2 has been added (at most two blocks, 64 SGPRs,
+// in flight).
 constexpr int kColBlockedFrom = 49;
 constexpr int kColRows = 8;
 
-template <int N>
-__device__ __forceinline__ void add_col_complex(double (&wr)[N], double (&wi)[N],
+// Adds rows [0, ROWS) of column j (of +A or -A, by sub) of the staged n x n
+// complex copy to the row sums.
+template <int N, int ROWS>
+__device__ __forceinline__ void add_col_complex(double (&wr)[ROWS], double (&wi)[ROWS],
                                         const double* __restrict__ staged, uint32_t sub, int j) {
   const double* base = staged + sub * (2 * N * N) + 2 * j * N;
-  if constexpr (N < kColBlockedFrom) {
+  if constexpr (ROWS < kColBlockedFrom) {
     cdptr col = as_const(base);
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
+    for (int i = 0; i < ROWS; ++i) {
       wr[i] += col[2 * i];
       wi[i] += col[2 * i + 1];
     }
   } else {
 #pragma unroll
-    for (int r0 = 0; r0 < N; r0 += kColRows) {
+    for (int r0 = 0; r0 < ROWS; r0 += kColRows) {
       const double* p = base + 2 * r0;
       if (r0 >= 2 * kColRows) p = after(p, wi[r0 - kColRows - 1]);
       cdptr col = as_const(p);
 #pragma unroll
-      for (int i = r0; i < r0 + kColRows && i < N; ++i) {
+      for (int i = r0; i < r0 + kColRows && i < ROWS; ++i) {
         wr[i] += col[2 * (i - r0)];
         wi[i] += col[2 * (i - r0) + 1];
       }
@@ -187,6 +190,207 @@ __device__ __forceinline__ cdd walk_chunk_complex(const double* __restrict__ sta
       const double s = rowabs[i];
       if (s > 0.0) drift = fmax(drift, hypot(wr[i] - fr[i], wi[i] - fi[i]) / s);
     }
+  }
+  return acc;
+}
+
+// ------------------------------------------------- rows kept in LDS ----
+// Above n = 48 the complex row sums alone (4n VGPRs) leave room for one wave
+// per SIMD, which cannot hide the latency of the scalar column loads and of
+// the FP64 chains.  The split walk keeps rows [0, R) in VGPRs and rows
+// [R, n) in LDS: one 16-byte slot per row and lane, row r of a wave's 64
+// lanes 1 KB contiguous (conflict-free).  In each pair an LDS row is read
+// once, multiplied into the products of both terms (before and after the
+// column-0 flip), takes the second flip and is written back: two LDS
+// accesses per LDS row and pair, each row's read issued while the row before
+// it is being used.  The VALU work is the same as in the register walk (the
+// two terms' products are split into the register rows' and the LDS rows'
+// and joined by one complex multiply each), the register rows' columns are
+// read as whole columns are up to n = 48, and the kernel runs two waves per
+// SIMD.
+constexpr int kSplitFrom = kColBlockedFrom;
+constexpr int kSplitRegRows = 46;
+
+template <int N>
+struct SplitRows {
+  static constexpr int R = N >= kSplitFrom ? kSplitRegRows : N;  // rows in VGPRs
+  static constexpr int L = N - R;                                // rows in LDS
+};
+
+// This lane's LDS slots: row r at [r * kWave].
+template <int L>
+__device__ __forceinline__ double2* lane_rows() {
+  __shared__ double2 s_rows[kWavesPerBlock * L * kWave];
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  return s_rows + wave * L * kWave + lane;
+}
+
+// (pr, pi) *= (xr, xi) in the product precision of MODE.
+template <int MODE>
+__device__ __forceinline__ void cmul_acc(double& pr, double& pi, double xr, double xi) {
+  if constexpr (MODE == 2) {
+    const float ar = (float)pr, ai = (float)pi, br = (float)xr, bi = (float)xi;
+    const float t = ai * bi, u = ai * br;
+    pr = (double)fmaf(ar, br, -t);
+    pi = (double)fmaf(ar, bi, u);
+  } else {
+    const double t = pi * xi, u = pi * xr;
+    const double nr = fma(pr, xr, -t);
+    const double ni = fma(pr, xi, u);
+    pr = nr;
+    pi = ni;
+  }
+}
+
+// Chunk start of the split walk: rows [0, R) into registers, rows [R, N)
+// into the lane's LDS slots (App. A, subpermanent, as form_w_complex).
+template <int N, int R>
+__device__ __forceinline__ void form_w_complex_split(const double* __restrict__ staged, uint64_t g,
+                                                     double (&wr)[R], double (&wi)[R],
+                                                     double2* __restrict__ rows) {
+  const uint64_t x = gray(g);
+  {
+    cdptr last = as_const(staged + 2 * (N - 1) * N);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      wr[i] = last[2 * i];
+      wi[i] = last[2 * i + 1];
+    }
+#pragma unroll 1
+    for (int j = 0; j < N - 1; ++j) {
+      const double d = ((x >> j) & 1) ? 1.0 : -1.0;
+      cdptr col = as_const(staged + 2 * j * N);
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        wr[i] = fma(d, col[2 * i], wr[i]);
+        wi[i] = fma(d, col[2 * i + 1], wi[i]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      wr[i] *= 0.5;
+      wi[i] *= 0.5;
+    }
+  }
+  constexpr int kB = 4;
+#pragma unroll
+  for (int r0 = R; r0 < N; r0 += kB) {
+    const double* base = opaque(staged);
+    double vr[kB], vi[kB];
+    cdptr last = as_const(base + 2 * (N - 1) * N + 2 * r0);
+#pragma unroll
+    for (int k = 0; k < kB; ++k)
+      if (r0 + k < N) {
+        vr[k] = last[2 * k];
+        vi[k] = last[2 * k + 1];
+      }
+#pragma unroll 1
+    for (int j = 0; j < N - 1; ++j) {
+      const double d = ((x >> j) & 1) ? 1.0 : -1.0;
+      cdptr col = as_const(base + 2 * j * N + 2 * r0);
+#pragma unroll
+      for (int k = 0; k < kB; ++k)
+        if (r0 + k < N) {
+          vr[k] = fma(d, col[2 * k], vr[k]);
+          vi[k] = fma(d, col[2 * k + 1], vi[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kB; ++k)
+      if (r0 + k < N) rows[(r0 - R + k) * kWave] = double2{0.5 * vr[k], 0.5 * vi[k]};
+  }
+}
+
+// The LDS rows' share of one pair: q0 = product before the column-0 flip,
+// q1 = after it; with UPDATE the rows then take the flip of column j (sign
+// subj) and are stored back.
+template <int N, int R, int MODE, bool UPDATE>
+__device__ __forceinline__ void lds_rows_pair(double2* __restrict__ rows,
+                                              const double* __restrict__ staged, uint32_t sub0,
+                                              uint32_t subj, int j, double& q0r, double& q0i,
+                                              double& q1r, double& q1i) {
+  constexpr int L = N - R;
+  const double* c0 = staged + sub0 * (2 * N * N) + 2 * R;
+  const double* cj = staged + subj * (2 * N * N) + 2 * j * N + 2 * R;
+  double tie[L];
+  double2 next = rows[0];  // each row's read is issued one row ahead
+#pragma unroll
+  for (int r0 = 0; r0 < L; r0 += kColRows) {
+    const double* p0 = c0 + 2 * r0;
+    const double* pj = cj + 2 * r0;
+    if (r0 >= 2 * kColRows) {
+      p0 = after(p0, tie[r0 - kColRows - 1]);
+      pj = after(pj, tie[r0 - kColRows - 1]);
+    }
+    cdptr a0 = as_const(p0);
+    cdptr aj = as_const(pj);
+#pragma unroll
+    for (int r = r0; r < r0 + kColRows && r < L; ++r) {
+      double2 v = next;
+      if (r + 1 < L) next = rows[(r + 1) * kWave];
+      if (r == 0) {
+        q0r = v.x;
+        q0i = v.y;
+      } else {
+        cmul_acc<MODE>(q0r, q0i, v.x, v.y);
+      }
+      v.x += a0[2 * (r - r0)];
+      v.y += a0[2 * (r - r0) + 1];
+      if (r == 0) {
+        q1r = v.x;
+        q1i = v.y;
+      } else {
+        cmul_acc<MODE>(q1r, q1i, v.x, v.y);
+      }
+      if constexpr (UPDATE) {
+        v.x += aj[2 * (r - r0)];
+        v.y += aj[2 * (r - r0) + 1];
+        rows[r * kWave] = v;
+      }
+      tie[r] = v.y;
+    }
+  }
+}
+
+// Signed sums of chunk G's terms with rows [R, N) in LDS (b >= 1).
+template <int N, int MODE>
+__device__ __forceinline__ cdd walk_chunk_complex_split(const double* __restrict__ staged,
+                                                        uint64_t G, int b, uint32_t gpar,
+                                                        double2* __restrict__ rows) {
+  constexpr int R = SplitRows<N>::R;
+  staged = opaque(staged);
+  double wr[R], wi[R];
+  form_w_complex_split<N, R>(staged, G << b, wr, wi, rows);
+  cdd acc{{0.0, 0.0}, {0.0, 0.0}};
+  const uint32_t half = 1u << (b - 1);
+  uint32_t t = 0;
+  for (; t + 1 < half; ++t) {
+    const uint32_t s1 = 2 * t + 2;
+    const int j = __builtin_ctz(s1);
+    const uint32_t subj = flip_subtracts(s1, j, b, gpar);
+    double q0r, q0i, q1r, q1i, p0r, p0i, p1r, p1i;
+    lds_rows_pair<N, R, MODE, true>(rows, staged, t & 1u, subj, j, q0r, q0i, q1r, q1i);
+    term_prod_complex<R, MODE>(wr, wi, p0r, p0i);
+    add_col_complex<N>(wr, wi, staged, t & 1u, 0);
+    term_prod_complex<R, MODE>(wr, wi, p1r, p1i);
+    add_col_complex<N>(wr, wi, staged, subj, j);
+    cmul_acc<MODE>(p0r, p0i, q0r, q0i);
+    cmul_acc<MODE>(p1r, p1i, q1r, q1i);
+    lane_acc<MODE>(acc.re, p1r - p0r);
+    lane_acc<MODE>(acc.im, p1i - p0i);
+  }
+  {
+    const uint32_t sub0 = (b >= 2) ? (t & 1u) : gpar;
+    double q0r, q0i, q1r, q1i, p0r, p0i, p1r, p1i;
+    lds_rows_pair<N, R, MODE, false>(rows, staged, sub0, 0u, 0, q0r, q0i, q1r, q1i);
+    term_prod_complex<R, MODE>(wr, wi, p0r, p0i);
+    add_col_complex<N>(wr, wi, staged, sub0, 0);
+    term_prod_complex<R, MODE>(wr, wi, p1r, p1i);
+    cmul_acc<MODE>(p0r, p0i, q0r, q0i);
+    cmul_acc<MODE>(p1r, p1i, q1r, q1i);
+    lane_acc<MODE>(acc.re, p1r - p0r);
+    lane_acc<MODE>(acc.im, p1i - p0i);
   }
   return acc;
 }

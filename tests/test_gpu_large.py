@@ -154,3 +154,29 @@ def test_large_complex_blocked_column_reads(B, orc, inp, n):
     r = B.perm_partial(dev_cm(A), picks[2] * L, 64 * L, log2_chunk=12, drift_check=True)
     assert 0.0 <= r.max_drift < 1e-12
     log(f"  complex n={n}: 6 chunks of 2^12, worst rel err {worst:.2e}, drift {r.max_drift:.1e}")
+
+
+@pytest.mark.parametrize("n", [49, 52, 55, 56, 60, 63, 64])
+def test_large_complex_rows_in_lds(B, orc, inp, n):
+    """From n = 49 the complex walk keeps rows 46.. of each lane's row sums in
+    LDS (the drift-checked walk keeps them all in registers).  Checked against
+    the oracle's direct terms in every precision, with one workgroup walking
+    many chunks in turn (each lane's LDS rows re-formed at every chunk start),
+    with chunks of 2 and 4 terms (the last pair alone, one pair before it),
+    and over 2^26 terms against the all-register walk."""
+    A = inp.complex_gaussian(n, 6400 + n, scale=n ** -0.5)
+    dA = dev_cm(A)
+    start = ((1 << (n - 1)) // 5) & ~((1 << 26) - 1)
+    want = val(orc.chunk_partial(A, start, 1 << 14))
+    for prec, tol in (("dd", TOL), ("fp64", TOL), ("split", 1e-3)):
+        got = B.perm_partial(dA, start, 1 << 14, log2_chunk=4, blocks=1, precision=prec)
+        assert rel(val(got), want) < tol, prec
+    small = val(orc.chunk_partial(A, start, 1 << 10))
+    for lc in (1, 2):
+        got = B.perm_partial(dA, start, 1 << 10, log2_chunk=lc)
+        assert rel(val(got), small) < TOL, lc
+    a = val(B.perm_partial(dA, start, 1 << 26, log2_chunk=12))
+    b = val(B.perm_partial(dA, start, 1 << 26, log2_chunk=12, drift_check=True))
+    assert rel(a, b) < 1e-12
+    log(f"  complex n={n} (rows in LDS): 2^14 terms in 1024 chunks on one workgroup, "
+        f"2^26 terms vs the register walk {rel(a, b):.1e}")
