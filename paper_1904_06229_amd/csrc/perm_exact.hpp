@@ -26,6 +26,22 @@ namespace exact {
 constexpr double kC51 = 15845632502852867518708790067200.0;  // 1.5 * 2^103
 constexpr double kM52 = 6755399441055744.0;                  // 1.5 * 2^52
 constexpr double kInv51 = 1.0 / 2251799813685248.0;          // 2^-51
+// 1.5 * 2^103 + 1.5 * 2^52: its bits span 2^103 .. 2^51, 53 bits, so the sum
+// is exact.
+constexpr double kC51M52 = kC51 + kM52;
+static_assert(kC51M52 - kC51 == kM52, "1.5*2^103 + 1.5*2^52 must be exact");
+
+// Low limb of an exact product, with the bin offset: for h = fl(x*g) with
+// |h| < 2^102, l = x*g - h and q = fl(h + 1.5*2^103), returns
+// (h - (q - 1.5*2^103)) + l + 1.5*2^52 exactly, whose bit pattern minus that
+// of 1.5*2^52 is the product modulo 2^51 in [-2^51, 2^51].  One subtraction
+// fewer than forming the remainder first: 1.5*2^103 + 1.5*2^52 - q equals
+// 1.5*2^52 - (q - 1.5*2^103), a multiple of 2^51 below 2^103 (exact), and the
+// two additions stay exact integers in (2^52, 2^53) because |h - (q -
+// 1.5*2^103)| <= 2^50 and |l| <= 2^49.
+__device__ __forceinline__ double low_limb(double h, double l, double q) {
+  return (h + (kC51M52 - q)) + l;
+}
 
 __device__ __forceinline__ uint64_t bits(double x) { return (uint64_t)__double_as_longlong(x); }
 
@@ -55,12 +71,12 @@ __device__ __forceinline__ void product_bins(const double (&G)[K], Bins& B) {
       const double h = G[0] * G[1];
       const double l = fma(G[0], G[1], -h);
       const double q = h + kC51;
-      const double hr = q - kC51;
       if constexpr (K == 2) {
         bin_put<ADD>(B.b1, bits(q));
-        bin_put<ADD>(B.b0, bits(((h - hr) + l) + kM52));
+        bin_put<ADD>(B.b0, bits(low_limb(h, l, q)));
         return;
       }
+      const double hr = q - kC51;
       X0 = (h - hr) + l;
       X1 = hr * kInv51;
     }
@@ -100,24 +116,20 @@ __device__ __forceinline__ void product_bins(const double (&G)[K], Bins& B) {
       const double h = X0 * Gl;
       const double l = fma(X0, Gl, -h);
       const double q = h + kC51;
-      const double hr = q - kC51;
-      bin_put<ADD>(B.b0, bits(((h - hr) + l) + kM52));
+      bin_put<ADD>(B.b0, bits(low_limb(h, l, q)));
       bin_put<ADD>(B.b1, bits(q));
     }
     {
       const double h = X1 * Gl;
       const double l = fma(X1, Gl, -h);
       const double q = h + kC51;
-      const double hr = q - kC51;
-      bin_put<ADD>(B.b1, bits(((h - hr) + l) + kM52));
+      bin_put<ADD>(B.b1, bits(low_limb(h, l, q)));
       bin_put<ADD>(B.b2, bits(q));
     }
     if constexpr (K >= 4) {
       const double h = X2 * Gl;
       const double l = fma(X2, Gl, -h);
-      const double q = h + kC51;
-      const double hr = q - kC51;
-      bin_put<ADD>(B.b2, bits(((h - hr) + l) + kM52));
+      bin_put<ADD>(B.b2, bits(low_limb(h, l, h + kC51)));
     }
   }
 }
