@@ -207,7 +207,9 @@ __device__ __forceinline__ cdd walk_chunk_complex(const double* __restrict__ sta
 // two terms' products are split into the register rows' and the LDS rows'
 // and joined by one complex multiply each), the register rows' columns are
 // read as whole columns are up to n = 48, and the kernel runs two waves per
-// SIMD.
+// SIMD.  46 register rows measured faster than fewer; at n = 49..52 the
+// optimiser keeps the few LDS rows in VGPRs across the pair loop, which also
+// measured faster than forcing their LDS accesses.
 constexpr int kSplitFrom = kColBlockedFrom;
 constexpr int kSplitRegRows = 46;
 
