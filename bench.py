@@ -67,7 +67,8 @@ KERNEL_SOURCES = {
     "real": ["kern_real.hip", "perm_walk.hpp"],
     "complex": ["kern_complex.hip", "perm_walk.hpp"],
     "band": ["kern_band.hip"],
-    "mixed": ["kern_mixed.hip", "perm_exact.hpp", "perm_cases_lo.inc", "perm_cases_hi.inc"],
+    "mixed": ["kern_mixed.hip", "perm_exact.hpp", "perm_walk.hpp", "perm_cases_lo.inc",
+              "perm_cases_hi.inc"],
     "batched": ["kern_batched.hip", "perm_walk.hpp"],
 }
 
@@ -144,7 +145,7 @@ def parse():
     p.add_argument("--workload", default="c3",
                    choices=["c1", "c2", "c3", "c4", "c5", "c6", "c7", "c8", "c9", "dense"])
     p.add_argument("--n", type=int, default=48,
-                   help="dense: matrix size (2..64)")
+                   help="dense: matrix size (2..64); c6: even size (4..64), n/2 columns x 2")
     p.add_argument("--kind", default="complex", choices=["complex", "real"],
                    help="dense: complex Ginibre/sqrt(n) or real N(0,1) entries")
     p.add_argument("--count", type=int, default=100000, help="c4: number of matrices")
@@ -187,6 +188,8 @@ def parse():
         p.error("--steps must be >= 1 and --warmup >= 0")
     if args.workload == "dense" and not 2 <= args.n <= 64:
         p.error("--n must be in 2..64")
+    if args.workload == "c6" and (args.n % 2 or not 4 <= args.n <= 64):
+        p.error("c6: --n must be even, in 4..64")
     return args
 
 
@@ -394,14 +397,17 @@ def bench_batched(args, standalone=True, sub_frac=0.01):
 
 
 def bench_repeated(args):
-    """48 photons leaving a 2304-mode Haar interferometer two per output in 24
-    outputs: per of the 48 x 48 matrix with 24 distinct columns of
-    multiplicity 2, by Eq. ryser2 (3^24 terms instead of 2^47)."""
+    """n photons (48 unless --n is given) leaving an n^2-mode Haar
+    interferometer two per output in n/2 outputs: per of the n x n matrix with
+    n/2 distinct columns of multiplicity 2, by Eq. ryser2 (3^(n/2) terms
+    instead of 2^(n-1)); with --terms-log2 K only the first 2^K terms of the
+    mixed-radix Gray order (perm_repeated_partial)."""
     import numpy as np
     import torch
     from paper_1904_06229_amd import binding as B, inputs
 
-    n, R, seed = 48, 24, 20190406
+    n, seed = args.n, 20190406
+    R = n // 2
     if args.calibrate_copy:
         calibrate_copy()
     U = inputs.haar_block(n, n * n, seed)
@@ -409,28 +415,39 @@ def bench_repeated(args):
     mult = [2] * R
     dC = torch.from_numpy(np.asfortranarray(C)).to("cuda")
     T = 3 ** R
+    count = min(T, 2 ** args.terms_log2) if args.terms_log2 else T
+    kw = {"blocks": args.blocks, "log2_chunk": args.log2_chunk}
+
+    def call():
+        if count < T:
+            return B.perm_repeated_partial(dC, mult, 0, count, **kw)
+        return B.perm_repeated(dC, mult, **kw)
+
     for _ in range(args.warmup):
-        r = B.perm_repeated(dC, mult, blocks=args.blocks, log2_chunk=args.log2_chunk)
+        r = call()
     torch.cuda.synchronize()
     kms = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        r = B.perm_repeated(dC, mult, blocks=args.blocks, log2_chunk=args.log2_chunk)
+        r = call()
         kms.append(r.kernel_ms)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     kavg = sum(kms) / len(kms)
     # per term: 2n row-sum updates, n-1 complex multiplies (4), weight (2), accumulate (2)
-    alg = 6.0 * n * T
+    alg = 6.0 * n * count
+    desc = (f"{n}x{n} complex, {R} distinct columns x 2 (first {R} columns of the {n} x {n * n} "
+            f"Haar block, seed {seed}), Eq. ryser2")
+    if count < T:
+        desc += f" -- PREFIX ONLY: first {count} of the {T} mixed-radix Gray terms"
     out = {
         "metric": "weighted Ryser terms/sec (n*prod(m_k+1)/s)",
-        "value": args.steps * n * float(T) / dt, "unit": "n*prod(m_k+1)/s", "n_gpus": 1,
+        "value": args.steps * n * float(count) / dt, "unit": "n*prod(m_k+1)/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"48x48 complex, 24 distinct columns x 2 (first 24 columns of "
-                               f"the 48 x 2304 Haar block, seed {seed}), Eq. ryser2",
-                   "n": n, "R": R, "terms": T, "inner_digits": r.log2_chunk, "blocks": r.blocks},
+        "config": {"workload": desc, "n": n, "R": R, "terms": count,
+                   "inner_digits": r.log2_chunk, "blocks": r.blocks},
         "roofline": {"bound": "alu", "achieved": alg / (kavg * 1e-3) / 1e12,
                      "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
                      "frac": alg / (kavg * 1e-3) / PEAK_LANE_OPS,
@@ -443,21 +460,21 @@ def bench_repeated(args):
         import oracle
         oracle.build(force=False)
         threads = oracle.default_threads()
-        count = 1 << 12
+        sample = 1 << 12
         while True:
             t1 = time.perf_counter()
-            want = oracle.ryser2_range(C, mult, 0, count, threads=threads)
+            want = oracle.ryser2_range(C, mult, 0, sample, threads=threads)
             cdt = time.perf_counter() - t1
-            if cdt >= 5.0 or count >= T:
+            if cdt >= 5.0 or sample >= T:
                 break
-            count = min(T, count * 2 ** max(1, min(8, int(math.log2(10.0 / max(cdt, 1e-4))))))
-        out["cpu_baseline"] = {"value": n * count / cdt, "unit": "n*prod(m_k+1)/s",
+            sample = min(T, sample * 2 ** max(1, min(8, int(math.log2(10.0 / max(cdt, 1e-4))))))
+        out["cpu_baseline"] = {"value": n * sample / cdt, "unit": "n*prod(m_k+1)/s",
                                "cores": threads, "kind": "oracle",
-                               "sample": f"first {count} of the {T} Gray terms, each formed "
+                               "sample": f"first {sample} of the {T} Gray terms, each formed "
                                          "directly (long double)", "seconds": round(cdt, 3)}
         # the same prefix on the GPU (outside the timed region)
-        g = B.perm_repeated_partial(dC, mult, 0, count)
-        out["oracle_check"] = {"range": f"mixed-radix Gray prefix [0, {count}) of {T}",
+        g = B.perm_repeated_partial(dC, mult, 0, sample)
+        out["oracle_check"] = {"range": f"mixed-radix Gray prefix [0, {sample}) of {T}",
                                "checked": True, "tolerance": 1e-10,
                                "rel_err_vs_oracle": complex_rel_err(g, want)}
     print(json.dumps(out))

@@ -25,7 +25,9 @@
 // step to step, so a pair of terms enters as P_s - P_{s+1} and the chunk sum
 // is multiplied by the sign of its first term at the end.
 #include "perm_device.hpp"
-#if !PERM_CPLX
+#if PERM_CPLX
+#include "perm_walk.hpp"
+#else
 #include "perm_exact.hpp"
 #endif
 
@@ -96,26 +98,28 @@ typedef const __attribute__((address_space(4))) uint64_t* cu64ptr;
 // counting digit), then each column adds its coefficient times itself to the
 // row sums (kind 0: f copies; kind 1: bit e of gray(f + 1)) and the digit's
 // first column multiplies the weight by omega_k(f_k).  One flat loop over
-// columns keeps a single copy of the row sums live.
+// columns keeps a single copy of the row sums live.  column_coef gives the
+// coefficient of staged column c (and updates the weight).
+__device__ __forceinline__ double column_coef(const MixArgs& a, uint64_t g, int c, double& W) {
+  ciptr dig = (ciptr)a.dig;
+  cu64ptr qabs = (cu64ptr)a.qabs;
+  const int k = dig[kDigColDigit * kMaxN + c];
+  const int e = dig[kDigColBit * kMaxN + c];
+  const uint32_t r = (uint32_t)dig[kDigRadix * kMaxN + k];
+  const uint64_t x = g / qabs[k];
+  const uint64_t hi = x / r;
+  const uint32_t dgt = (uint32_t)(x - hi * r);
+  const uint32_t f = (hi & 1) ? r - 1u - dgt : dgt;
+  if (e == 0) W *= a.omega[dig[kDigWofs * kMaxN + k] + f];
+  const uint32_t sub = (f + 1u) ^ ((f + 1u) >> 1);
+  return dig[kDigKind * kMaxN + k] == 0 ? (double)f : (double)((sub >> e) & 1u);
+}
+
 template <int N>
 __device__ __forceinline__ void outer_digits(const MixArgs& a, const double* staged, uint64_t g,
                                              int c0, Rows<N>& w, double& W) {
-  ciptr dig = (ciptr)a.dig;
-  cu64ptr qabs = (cu64ptr)a.qabs;
 #pragma unroll 1
-  for (int c = c0; c < a.ncols; ++c) {
-    const int k = dig[kDigColDigit * kMaxN + c];
-    const int e = dig[kDigColBit * kMaxN + c];
-    const uint32_t r = (uint32_t)dig[kDigRadix * kMaxN + k];
-    const uint64_t x = g / qabs[k];
-    const uint64_t hi = x / r;
-    const uint32_t dgt = (uint32_t)(x - hi * r);
-    const uint32_t f = (hi & 1) ? r - 1u - dgt : dgt;
-    if (e == 0) W *= a.omega[dig[kDigWofs * kMaxN + k] + f];
-    const uint32_t sub = (f + 1u) ^ ((f + 1u) >> 1);
-    const double coef = dig[kDigKind * kMaxN + k] == 0 ? (double)f : (double)((sub >> e) & 1u);
-    add_col_times<N>(w, staged, c, coef);
-  }
+  for (int c = c0; c < a.ncols; ++c) add_col_times<N>(w, staged, c, column_coef(a, g, c, W));
 }
 
 // Exact product of a double-double by a double (TwoProduct on the high part).
@@ -192,6 +196,106 @@ __device__ __forceinline__ Acc walk_chunk(const MixArgs& a, uint64_t c, uint32_t
   }
   return Acc{dd_scale(acc.re, W), dd_scale(acc.im, W)};
 }
+
+#if PERM_CPLX
+// ------------------------------------------------- rows kept in LDS ----
+// From n = kSplitFrom the complex chunk walk keeps rows [R, n) of each lane's
+// row sums in LDS, as the dense complex walk does (perm_walk.hpp): the rows
+// in VGPRs then leave room for two waves per SIMD instead of one.  At the
+// chunk start every outer column updates the LDS rows in place (its
+// coefficient is formed once per column, as in outer_digits); in the walk each
+// LDS row is read once per pair of terms, multiplied into both terms'
+// products and written back after the pair's second column.
+template <int R>
+__device__ __forceinline__ void add_col_rows(double (&wr)[R], double (&wi)[R], const double* col) {
+  cdptr c = as_const(col);
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    wr[i] += c[2 * i];
+    wi[i] += c[2 * i + 1];
+  }
+}
+
+template <int N>
+__device__ __forceinline__ Acc walk_chunk_split(const MixArgs& a, uint64_t c, uint32_t par,
+                                                double2* __restrict__ rows) {
+  constexpr int R = SplitRows<N>::R, L = SplitRows<N>::L;
+  const double* staged = opaque(a.staged);
+  const uint64_t g = c * (uint64_t)a.L;
+  double wr[R], wi[R];
+  {
+    cdptr st = as_const(staged + kCw * (2 * (a.ncols + 1) + (int)par) * N);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      wr[i] = st[2 * i];
+      wi[i] = st[2 * i + 1];
+    }
+#pragma unroll
+    for (int r = 0; r < L; ++r) rows[r * kWave] = double2{st[2 * (R + r)], st[2 * (R + r) + 1]};
+  }
+  double W = 1.0;
+#pragma unroll 1
+  for (int k = a.outer_col; k < a.ncols; ++k) {
+    const double f = column_coef(a, g, k, W);
+    cdptr col = as_const(staged + kCw * k * N);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      wr[i] = fma(f, col[2 * i], wr[i]);
+      wi[i] = fma(f, col[2 * i + 1], wi[i]);
+    }
+#pragma unroll
+    for (int r = 0; r < L; ++r) {
+      double2 v = rows[r * kWave];
+      v.x = fma(f, col[2 * (R + r)], v.x);
+      v.y = fma(f, col[2 * (R + r) + 1], v.y);
+      rows[r * kWave] = v;
+    }
+  }
+  cdptr tin = as_const(a.tin + par * (uint32_t)a.L);
+  ciptr toff = (ciptr)(a.toff + par * (uint32_t)a.L);
+  Acc acc{{0.0, 0.0}, {0.0, 0.0}};
+  const int Lc = a.L;
+  int s = 0;
+  for (; s + 1 < Lc; s += 2) {
+    const double t0 = tin[s], t1 = tin[s + 1];
+    const int32_t o0 = toff[s], o1 = toff[s + 1];
+    double q0r, q0i, q1r, q1i, p0r, p0i, p1r, p1i;
+    lds_rows_pair<N, R, 0, true>(rows, staged + o0 + 2 * R, staged + o1 + 2 * R, q0r, q0i, q1r,
+                                 q1i);
+    prod_c64<R>(wr, wi, p0r, p0i);
+    add_col_rows<R>(wr, wi, staged + o0);
+    // as in walk_chunk: one column's scalar loads at a time
+    __builtin_amdgcn_sched_barrier(0);
+    prod_c64<R>(wr, wi, p1r, p1i);
+    add_col_rows<R>(wr, wi, staged + o1);
+    __builtin_amdgcn_sched_barrier(0);
+    cmul_acc<0>(p0r, p0i, q0r, q0i);
+    cmul_acc<0>(p1r, p1i, q1r, q1i);
+    dd_acc(acc.re, fma(t1, p1r, t0 * p0r));
+    dd_acc(acc.im, fma(t1, p1i, t0 * p0i));
+  }
+  if (s < Lc) {  // odd L: the last term has no partner (only its product is used)
+    const double* cz = staged + toff[s] + 2 * R;
+    double q0r, q0i, q1r, q1i, pr, pi;
+    lds_rows_pair<N, R, 0, false>(rows, cz, cz, q0r, q0i, q1r, q1i);
+    prod_c64<R>(wr, wi, pr, pi);
+    cmul_acc<0>(pr, pi, q0r, q0i);
+    dd_acc(acc.re, tin[s] * pr);
+    dd_acc(acc.im, tin[s] * pi);
+  }
+  return Acc{dd_scale(acc.re, W), dd_scale(acc.im, W)};
+}
+
+template <int N, bool SINGLE>
+constexpr bool mix_split() {
+  return N >= kSplitFrom && !SINGLE;
+}
+#else
+template <int N, bool SINGLE>
+constexpr bool mix_split() {
+  return false;
+}
+#endif
 
 #if !PERM_CPLX
 __device__ __forceinline__ u128 u128_neg(u128 v) {
@@ -323,11 +427,17 @@ __global__ __launch_bounds__(kBlock) void mix_exact_kernel(MixArgs a) {
 #endif
 
 template <int N, bool SINGLE>
-__global__ __launch_bounds__(kBlock) void mix_walk_kernel(MixArgs a) {
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(mix_split<N, SINGLE>() ? 2 : 1)))
+void mix_walk_kernel(MixArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint64_t wave = wave_id();
   const uint64_t nwaves = (uint64_t)gridDim.x * kWavesPerBlock;
   dd re{0.0, 0.0}, im{0.0, 0.0};
+#if PERM_CPLX
+  double2* rows = nullptr;
+  if constexpr (mix_split<N, SINGLE>()) rows = lane_rows<SplitRows<N>::L>();
+#endif
   if (a.status[0] == kStOk) {
     for (uint64_t task = wave; task < a.ntasks; task += nwaves) {
       const uint64_t c = task_chunk(task, lane);
@@ -336,7 +446,12 @@ __global__ __launch_bounds__(kBlock) void mix_walk_kernel(MixArgs a) {
         part = single_term<N>(a, a.first + c);
       } else {
         const uint32_t par = (uint32_t)((a.first + (task & 1)) & 1);
-        part = walk_chunk<N>(a, a.first + c, par);
+#if PERM_CPLX
+        if constexpr (mix_split<N, SINGLE>())
+          part = walk_chunk_split<N>(a, a.first + c, par, rows);
+        else
+#endif
+          part = walk_chunk<N>(a, a.first + c, par);
       }
       if (c < a.nchunks) {
         re = dd_add(re, part.re);

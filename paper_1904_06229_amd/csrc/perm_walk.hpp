@@ -304,29 +304,28 @@ __device__ __forceinline__ void form_w_complex_split(const double* __restrict__ 
   }
 }
 
-// The LDS rows' share of one pair: q0 = product before the column-0 flip,
-// q1 = after it; with UPDATE the rows then take the flip of column j (sign
-// subj) and are stored back.
+// The LDS rows' share of one pair: q0 = product of the rows before the first
+// flip (the column at c0), q1 = after it; with UPDATE the rows then take the
+// second flip (the column at c1) and are stored back.  c0 and c1 point at row
+// R of their (interleaved complex) columns; c1 is not read without UPDATE.
 template <int N, int R, int MODE, bool UPDATE>
 __device__ __forceinline__ void lds_rows_pair(double2* __restrict__ rows,
-                                              const double* __restrict__ staged, uint32_t sub0,
-                                              uint32_t subj, int j, double& q0r, double& q0i,
-                                              double& q1r, double& q1i) {
+                                              const double* __restrict__ c0,
+                                              const double* __restrict__ c1, double& q0r,
+                                              double& q0i, double& q1r, double& q1i) {
   constexpr int L = N - R;
-  const double* c0 = staged + sub0 * (2 * N * N) + 2 * R;
-  const double* cj = staged + subj * (2 * N * N) + 2 * j * N + 2 * R;
   double tie[L];
   double2 next = rows[0];  // each row's read is issued one row ahead
 #pragma unroll
   for (int r0 = 0; r0 < L; r0 += kColRows) {
     const double* p0 = c0 + 2 * r0;
-    const double* pj = cj + 2 * r0;
+    const double* p1 = c1 + 2 * r0;
     if (r0 >= 2 * kColRows) {
       p0 = after(p0, tie[r0 - kColRows - 1]);
-      pj = after(pj, tie[r0 - kColRows - 1]);
+      p1 = after(p1, tie[r0 - kColRows - 1]);
     }
     cdptr a0 = as_const(p0);
-    cdptr aj = as_const(pj);
+    cdptr a1 = as_const(p1);
 #pragma unroll
     for (int r = r0; r < r0 + kColRows && r < L; ++r) {
       double2 v = next;
@@ -346,8 +345,8 @@ __device__ __forceinline__ void lds_rows_pair(double2* __restrict__ rows,
         cmul_acc<MODE>(q1r, q1i, v.x, v.y);
       }
       if constexpr (UPDATE) {
-        v.x += aj[2 * (r - r0)];
-        v.y += aj[2 * (r - r0) + 1];
+        v.x += a1[2 * (r - r0)];
+        v.y += a1[2 * (r - r0) + 1];
         rows[r * kWave] = v;
       }
       tie[r] = v.y;
@@ -372,7 +371,9 @@ __device__ __forceinline__ cdd walk_chunk_complex_split(const double* __restrict
     const int j = __builtin_ctz(s1);
     const uint32_t subj = flip_subtracts(s1, j, b, gpar);
     double q0r, q0i, q1r, q1i, p0r, p0i, p1r, p1i;
-    lds_rows_pair<N, R, MODE, true>(rows, staged, t & 1u, subj, j, q0r, q0i, q1r, q1i);
+    lds_rows_pair<N, R, MODE, true>(rows, staged + (t & 1u) * (2 * N * N) + 2 * R,
+                                    staged + subj * (2 * N * N) + 2 * j * N + 2 * R, q0r, q0i,
+                                    q1r, q1i);
     term_prod_complex<R, MODE>(wr, wi, p0r, p0i);
     add_col_complex<N>(wr, wi, staged, t & 1u, 0);
     term_prod_complex<R, MODE>(wr, wi, p1r, p1i);
@@ -385,7 +386,8 @@ __device__ __forceinline__ cdd walk_chunk_complex_split(const double* __restrict
   {
     const uint32_t sub0 = (b >= 2) ? (t & 1u) : gpar;
     double q0r, q0i, q1r, q1i, p0r, p0i, p1r, p1i;
-    lds_rows_pair<N, R, MODE, false>(rows, staged, sub0, 0u, 0, q0r, q0i, q1r, q1i);
+    const double* c0 = staged + sub0 * (2 * N * N) + 2 * R;
+    lds_rows_pair<N, R, MODE, false>(rows, c0, c0, q0r, q0i, q1r, q1i);
     term_prod_complex<R, MODE>(wr, wi, p0r, p0i);
     add_col_complex<N>(wr, wi, staged, sub0, 0);
     term_prod_complex<R, MODE>(wr, wi, p1r, p1i);

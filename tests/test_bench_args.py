@@ -36,7 +36,10 @@ def test_defaults(monkeypatch):
 
 @pytest.mark.parametrize("argv", [["--workload", "c5", "--checkpoint", "c", "--steps", "2"],
                                   ["--workload", "c5", "--checkpoint", "c", "--warmup", "1"],
-                                  ["--steps", "0"], ["--warmup", "-1"]])
+                                  ["--steps", "0"], ["--warmup", "-1"],
+                                  ["--workload", "c6", "--n", "47"],
+                                  ["--workload", "c6", "--n", "66"],
+                                  ["--workload", "dense", "--n", "65"]])
 def test_rejected(argv, monkeypatch):
     with pytest.raises(SystemExit):
         parse(argv, monkeypatch)

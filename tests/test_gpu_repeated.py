@@ -244,3 +244,31 @@ def test_errors(B):
     # 64 distinct columns: 2^64 terms, beyond the index range (the dense path covers it)
     with pytest.raises(B.PermError):
         B.perm_repeated(dev(np.ones((64, 64))), [1] * 64)
+
+
+def mixed_mult(n, seed, lead):
+    """Multiplicities summing to n: `lead` first, then 1..3 drawn from a seed."""
+    r = np.random.default_rng(seed)
+    mult = list(lead)
+    while sum(mult) < n:
+        mult.append(int(min(r.integers(1, 4), n - sum(mult))))
+    return mult
+
+
+@pytest.mark.parametrize("n", [49, 52, 56, 60, 64])
+def test_large_complex_rows_in_lds(B, orc, n):
+    """From n = 49 the complex walk of Eq. ryser2 keeps rows 46.. of each
+    lane's row sums in LDS.  Ranges of the reflected mixed-radix Gray order
+    against the oracle's range form: one workgroup walking many chunks in turn
+    (the LDS rows re-formed at every chunk start), chunks of odd length (nine
+    terms: the unpaired last term), and the default plan."""
+    for lead, lc, blocks in (([1, 1, 1, 1], 4, 1), ([2, 2], 4, 1), ([3, 1], 0, 0)):
+        mult = mixed_mult(n, 700 + n, lead)
+        C = columns(n, mult, 800 + n, True)
+        T = math.prod(m + 1 for m in mult)
+        dC = dev(C)
+        for start, count in ((0, 1 << 14), (T // 3, 3000), (T - (1 << 13), 1 << 13)):
+            got = B.perm_repeated_partial(dC, mult, start, count, log2_chunk=lc, blocks=blocks)
+            want = orc.ryser2_range(C, mult, start, count)
+            assert rel(val(got), val(want)) < TOL, (lead, start, count)
+    log(f"  complex n={n} (rows in LDS): Eq. ryser2 ranges match the oracle")
