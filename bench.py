@@ -46,7 +46,8 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 SEED_C2 = 20190413
 
 
-def algorithmic_ops_per_term(kind: str, n: int, col0_nonzeros: int = 0) -> float:
+def algorithmic_ops_per_term(kind: str, n: int, col0_nonzeros: int = 0,
+                             walk_variant: int = 0) -> float:
     """VALU lane-operations the method needs per Gray term (App. A, subpermanent):
     n row-sum updates, n-1 multiplies, 1 signed accumulate (complex: 2n updates,
     n-1 complex multiplies of 4 ops, 2 accumulates).
@@ -54,9 +55,19 @@ def algorithmic_ops_per_term(kind: str, n: int, col0_nonzeros: int = 0) -> float
     The pair-shared 0/1 walk evaluates the two terms of a pair as S (D1 - D0):
     per pair m + n updates (m = ones in the flipped column), n - M - 1 static
     multiplies (M = n // 3), 2 (M - 1) dynamic ones, one subtraction, one
-    multiply by S and one accumulate: 2n + m + M per pair."""
+    multiply by S and one accumulate: 2n + m + M per pair.
+
+    The banded walk (walk_variant 2) takes two pairs as S' E (D1 - D0) each,
+    S' shared (E = (n - M) // 2 rows): per quad n + M + E + 2m updates,
+    n - M - E - 1 shared multiplies, and per pair E - 1 + 2 (M - 1) dynamic
+    ones, one subtraction, two multiplies by S' and E and one accumulate:
+    2n + 4M + 2E + 2m + 1 per quad."""
     if kind == "complex":
         return 2 * n + 4 * (n - 1) + 2
+    if col0_nonzeros and walk_variant == 2:
+        M = n // 3
+        E = (n - M) // 2
+        return (2 * n + 4 * M + 2 * E + 2 * col0_nonzeros + 1) / 4.0
     if col0_nonzeros:
         return (2 * n + col0_nonzeros + n // 3) / 2.0
     return 2 * n
@@ -889,7 +900,8 @@ def main():
     per_perm = n * float(terms)
     value = args.steps * per_perm / dt
     kavg = sum(kms) / len(kms)
-    alg = algorithmic_ops_per_term(kind, n, getattr(r, "col0_nonzeros", 0)) * float(terms)
+    alg = algorithmic_ops_per_term(kind, n, getattr(r, "col0_nonzeros", 0),
+                                   getattr(r, "walk_variant", 0)) * float(terms)
     achieved = alg / (kavg * 1e-3)
     kernel = f"walk_{kind}_kernel<{n}>"
     if kind != "int01" and r.walk_variant == 1:  # staging, walk and finish in one launch

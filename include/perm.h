@@ -119,14 +119,15 @@ typedef struct {
                             the call on the host, from entry until the result is in host
                             memory.  perm_repeated*, perm_sparse*: HIP events on `stream`
                             from staging to the result */
-  int32_t walk_variant;  /* perm_int01: 1 if the pair-shared walk ran, else 0.  perm_real,
+  int32_t walk_variant;  /* perm_int01: 2 if the banded pair walk ran, 1 if the pair-shared
+                            walk ran, else 0.  perm_real,
                             perm_complex: 1 if the one-launch path ran (n <= 24 with
                             default blocks and no drift check: staging, walk and the
                             fixed-order sum in one kernel), else 0.  perm_sparse
                             with PERM_DT_INT01: the row groups of the exact product (1..4),
                             or 0 for the size-only grouping.  Otherwise 0 */
-  int32_t col0_nonzeros; /* 0/1 path, pair-shared walk: ones in the column flipped between the
-                            two terms of every pair; otherwise 0 */
+  int32_t col0_nonzeros; /* 0/1 path, pair-shared or banded walk: ones in the column flipped
+                            between the two terms of every pair; otherwise 0 */
   int32_t parts;         /* partial sums the result was added from (the records written
                             to opts->partials_out when it is given) */
   int32_t pad;
@@ -167,7 +168,12 @@ perm_status perm_complex(const double* dA, int n, int ld, const perm_opts* opts,
  *   n/3 rows' sums multiply to less than 2^50, the two terms of every pair
  *   share the product of the other rows and one exact combination
  *   (walk_variant = 1): about 40% fewer operations per term for 0/1 matrices
- *   of density 1/2.
+ *   of density 1/2.  The column with the fewest ones outside those rows then
+ *   becomes the column flipped after every other pair, the rows with a one
+ *   there follow, up to (n - n/3)/2 rows; when it has at most that many ones
+ *   there and those rows' sums, and the remaining rows' sums, each multiply to
+ *   less than 2^50, the product of the remaining rows is shared by two pairs
+ *   and that flip skips them (walk_variant = 2): about 10% fewer again.
  * Errors: PERM_EINVAL (sizes, or an entry other than 0/1), PERM_ERANGE, PERM_EHIP.
  */
 perm_status perm_int01(const uint8_t* dA, int n, int ld, const perm_opts* opts,

@@ -157,9 +157,87 @@ __device__ __forceinline__ u128 walk_chunk_pairs(const double* __restrict__ stag
   return fold(B);
 }
 
-// VARIANT 0: plain walk; VARIANT 1: the pair-shared walk when status[1] (set
-// by the staging kernel) allows it, else the plain walk -- one launch, a
-// wave-uniform branch.
+// ---------------------------------------------------------- banded ----
+// Column 1 is flipped after every other pair (the flip after pair t is column
+// ctz(2t + 2)).  The staging kernel places after group D (rows 0..M-1) the
+// rows with a one in column 1 and pads them to E = (N - M) / 2 rows (group
+// E); the remaining rows S' have zeros in columns 0 and 1.  In a quad of
+// pairs (2u, 2u + 1) S' is therefore unchanged: its product is formed once per
+// quad, and the column-1 flip between the two pairs touches rows 0..M+E-1
+// only.  Each pair contributes S' E (D1 - D0), the three factors exact below
+// 2^50 (the staging kernel checks the degree products of E and S') and
+// combined into the bins as in the pair-shared walk.
+template <int N>
+constexpr int band_rows() {
+  return (N - pair_rows<N>()) / 2;
+}
+
+template <int N, int M, int E>
+__device__ __forceinline__ void band_pair(double (&r)[N], const double* __restrict__ staged,
+                                          uint32_t sub0, double gs, Bins& B) {
+  double G[3];
+  G[0] = gs;
+  G[1] = rows_prod<N, M, M + E>(r);
+  const double D0 = rows_prod<N, 0, M>(r);
+  cdptr col = as_const(staged + sub0 * (N * N));  // column 0; zero below row M
+#pragma unroll
+  for (int i = 0; i < M; ++i) r[i] += col[i];
+  const double D1 = rows_prod<N, 0, M>(r);
+  G[2] = D1 - D0;
+  product_bins<3, true>(G, B);
+}
+
+// Rows 0..ROWS-1 of column j (the rows below have zeros there).
+template <int N, int ROWS>
+__device__ __forceinline__ void add_col_rows(double (&r)[N], const double* __restrict__ staged,
+                                             uint32_t sub, int j) {
+  cdptr col = as_const(staged + sub * (N * N) + j * N);
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) r[i] += col[i];
+}
+
+// Chunk G (b >= 2: whole quads; in a quad the column-0 flip of the first pair
+// adds the column and that of the second subtracts it, as t & 1 says for
+// pairs t = 2u and 2u + 1).
+template <int N>
+__device__ __forceinline__ u128 walk_chunk_band(const double* __restrict__ staged, uint64_t G,
+                                                int b, uint32_t gpar) {
+  constexpr int M = pair_rows<N>();
+  constexpr int E = band_rows<N>();
+  constexpr int S0 = M + E;
+  staged = opaque(staged);
+  double r[N];
+  form_w_real<N>(staged, G << b, r);
+  Bins B{0, 0, 0};
+  const uint32_t half = 1u << (b - 1);
+  uint32_t t = 0;
+  for (; t + 2 < half; t += 2) {
+    const double gs = rows_prod<N, S0, N>(r);
+    band_pair<N, M, E>(r, staged, 0u, gs, B);
+    add_col_rows<N, S0>(r, staged, flip_subtracts(2 * t + 2, 1, b, gpar), 1);
+    band_pair<N, M, E>(r, staged, 1u, gs, B);
+    const uint32_t s1 = 2 * t + 4;
+    const int j = __builtin_ctz(s1);
+    add_col<N>(r, staged, flip_subtracts(s1, j, b, gpar), j);
+  }
+  {  // last quad: no flip after it
+    const double gs = rows_prod<N, S0, N>(r);
+    band_pair<N, M, E>(r, staged, 0u, gs, B);
+    add_col_rows<N, S0>(r, staged, flip_subtracts(2 * t + 2, 1, b, gpar), 1);
+    band_pair<N, M, E>(r, staged, 1u, gs, B);
+  }
+  // every pair entered its bit patterns with a + sign: remove the offsets
+  const Bins off = product_offsets<3>();
+  B.b0 -= (uint64_t)half * off.b0;
+  B.b1 -= (uint64_t)half * off.b1;
+  B.b2 -= (uint64_t)half * off.b2;
+  return fold(B);
+}
+
+// VARIANT 0: plain walk; VARIANT 1: by status[1] (set by the staging
+// kernel), the banded walk (2, chunks of at least 4 terms), the pair-shared
+// walk (1, or 2 with 2-term chunks) or the plain walk -- one launch,
+// wave-uniform branches.
 template <int N, bool DRIFT, bool SINGLE, int VARIANT>
 __global__ __launch_bounds__(kBlock) void walk_int01_kernel(WalkArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -168,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void walk_int01_kernel(WalkArgs a) {
   u128 acc{0, 0};
   double drift = 0.0;
   if (a.status[0] == kStOk) {
-    const bool pairs = VARIANT == 1 && a.status[1] == 1;
+    const int pv = VARIANT == 1 ? a.status[1] : 0;
     for (uint64_t task = wave; task < a.ntasks; task += nwaves) {
       const uint64_t c = task_chunk(task, lane);
       const uint32_t gpar = (uint32_t)((a.first + (task & 1)) & 1);
@@ -177,7 +255,9 @@ __global__ __launch_bounds__(kBlock) void walk_int01_kernel(WalkArgs a) {
       if constexpr (SINGLE) {
         part = single_term<N>(a.staged, a.first + c);
       } else if constexpr (VARIANT == 1) {
-        if (pairs)
+        if (pv == 2 && a.b >= 2)
+          part = walk_chunk_band<N>(a.staged, a.first + c, a.b, gpar);
+        else if (pv >= 1)
           part = walk_chunk_pairs<N>(a.staged, a.first + c, a.b, gpar);
         else
           part = walk_chunk<N, DRIFT>(a.staged, a.first + c, a.b, gpar, dr);

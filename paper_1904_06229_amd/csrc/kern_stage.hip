@@ -123,15 +123,23 @@ __global__ __launch_bounds__(kBlock) void stage_float_kernel(const double* __res
 // terms, not the total) the copy is permuted: the column with the fewest
 // ones becomes column 0 (the column flipped between the two terms of every
 // pair), the rows with a one there come first, then the other rows by
-// ascending degree.  status[1] = 1 when that column has at most M ones and
-// the first M rows' degrees multiply to less than 2^50, i.e. when the
-// pair-shared walk is exact; status[2] = the number of ones in column 0.
+// ascending degree up to M rows (group D).  Column 1 (flipped after every
+// other pair) becomes the column with the fewest ones outside D; the rows
+// after D are those with a one in it, then the others, each by ascending
+// degree.  With E = (n - M) / 2, rows M .. M+E-1 form group E and the rest
+// group S', whose rows have zeros in columns 0 and 1.  status[1] = 1 when
+// column 0 has at most M ones and D's degrees multiply to less than 2^50
+// (the pair-shared walk is exact); 2 when moreover column 1 has at most E ones
+// outside D and the degrees of E and of S' each multiply to less than 2^50
+// (the banded walk is exact); status[2] = the number of ones in column 0.
 __global__ __launch_bounds__(kBlock) void stage_int01_kernel(const uint8_t* __restrict__ A, int n,
                                                              int ld, int range_check,
                                                              int pair_rows, double* staged,
                                                              double* rowabs, int32_t* rowexp,
                                                              int32_t* status, double* bound) {
   __shared__ uint8_t s_a[kMaxN * kMaxN];  // s_a[i * kMaxN + j] = a_ij
+  __shared__ uint64_t s_cmask[kMaxN];      // bit i of s_cmask[j]: a_ij != 0
+  __shared__ uint64_t s_less[kMaxN];       // bit q of s_less[i]: row q before row i by degree
   __shared__ int32_t s_row[kMaxN], s_col[kMaxN], s_deg[kMaxN], s_csum[kMaxN];
   __shared__ double s_term[kMaxN];
   __shared__ double s_lg[kMaxN + 1];      // log2(k)
@@ -160,6 +168,9 @@ __global__ __launch_bounds__(kBlock) void stage_int01_kernel(const uint8_t* __re
         bad |= v[u] > 1;
         s_a[i * kMaxN + j] = v[u];
       }
+      // the wave holds all rows of column j: its rows with a one, as a mask
+      const uint64_t m = __ballot(i < n && j < n && v[u] != 0);
+      if (i == 0 && j < n) s_cmask[j] = m;
     }
     if (bad) atomicOr(&s_bad, 1);
   }
@@ -180,9 +191,12 @@ __global__ __launch_bounds__(kBlock) void stage_int01_kernel(const uint8_t* __re
     for (int i = 0; i < n; ++i) c += s_a[i * kMaxN + j];
     s_csum[j] = c;
   }
-  __shared__ int32_t s_best;
+  __shared__ int32_t s_best, s_col1, s_ones1;
+  __shared__ int32_t s_pos[kMaxN];  // place of row i in the staged order (group D)
+  __shared__ uint64_t s_outd;       // the rows outside group D, as a mask
   __syncthreads();
   const bool permute = pair_rows > 0 && !s_bad;
+  const int band = (n - pair_rows) / 2;  // rows of group E
   // the sparsest column (lowest index among equals): one wave's min-reduction
   if (permute && tid < kWave) {
     int key = tid < n ? (s_csum[tid] << 8) | tid : 0x7fffffff;
@@ -193,32 +207,77 @@ __global__ __launch_bounds__(kBlock) void stage_int01_kernel(const uint8_t* __re
   __syncthreads();
   if (permute && tid < n) {
     const int best = s_best;
-    // columns: the sparsest first, the others in their order
-    s_col[tid == 0 ? 0 : tid] = tid == 0 ? best : (tid <= best ? tid - 1 : tid);
     // rows: those with a one in the sparsest column first (in index order), then
     // the others by ascending degree (index order among equals); each row's
     // place is the number of rows that precede it
     const int i = tid;
-    const bool top = s_a[i * kMaxN + best] != 0;
-    int rank = 0;
-    for (int q = 0; q < n; ++q) {
-      const bool qtop = s_a[q * kMaxN + best] != 0;
-      if (top)
-        rank += (qtop && q < i) ? 1 : 0;
-      else
-        rank += (qtop || s_deg[q] < s_deg[i] || (s_deg[q] == s_deg[i] && q < i)) ? 1 : 0;
-    }
+    const uint64_t topm = s_cmask[best];
+    const bool top = (topm >> i) & 1;
+    uint64_t less = 0;  // rows before row i by (degree, index)
+    for (int q = 0; q < n; ++q)
+      if (s_deg[q] < s_deg[i] || (s_deg[q] == s_deg[i] && q < i)) less |= 1ull << q;
+    const uint64_t below = i ? (~0ull >> (kMaxN - i)) : 0ull;  // rows 0..i-1
+    const int rank = top ? __popcll(topm & below) : __popcll(topm) + __popcll(less & ~topm);
     s_row[rank] = i;
+    s_pos[i] = rank;
+    s_less[i] = less;
+  }
+  __syncthreads();
+  if (permute && tid < kWave) {
+    const uint64_t outd = __ballot(tid < n && s_pos[tid] >= pair_rows);
+    // column 1: the fewest ones outside group D (lowest index among equals)
+    const int c1 = tid < n ? __popcll(s_cmask[tid] & outd) : 0;
+    int key = (tid < n && tid != s_best) ? (c1 << 8) | tid : 0x7fffffff;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) key = min(key, __shfl_xor(key, off));
+    if (tid == 0) {
+      s_col1 = key & 0xff;
+      s_ones1 = key >> 8;
+      s_outd = outd;
+    }
+  }
+  __syncthreads();
+  if (permute && tid < n) {
+    const int best = s_best, col1 = s_col1;
+    // columns: the sparsest, then column 1, then the others in their order
+    int src = best;
+    if (tid == 1) {
+      src = col1;
+    } else if (tid >= 2) {
+      int k = tid - 2;
+      for (src = 0; src == best || src == col1 || k-- > 0; ++src) {
+      }
+    }
+    s_col[tid] = src;
+    // rows after group D: a one in column 1 first, then the others, each by
+    // ascending degree (index order among equals)
+    const int i = tid;
+    const uint64_t outd = s_outd;
+    if ((outd >> i) & 1) {
+      const uint64_t em = s_cmask[col1] & outd;  // outside D with a one in column 1
+      const uint64_t less = s_less[i];
+      const int rank = pair_rows + (((em >> i) & 1) ? __popcll(less & em)
+                                                     : __popcll(em) + __popcll(less & outd & ~em));
+      s_row[rank] = i;
+    }
   }
   __syncthreads();
   if (tid == 0) {
     int pairs_ok = 0, ones0 = 0;
     if (permute) {
+      // degree products are exact while below 2^53; only compared with 2^50
+      auto degprod = [&](int lo, int hi) {
+        double prod = 1.0;
+        for (int i = lo; i < hi; ++i) prod *= (double)s_deg[s_row[i]];
+        return prod;
+      };
+      constexpr double k2p50 = 1125899906842624.0;
       ones0 = s_csum[s_best];
-      if (ones0 <= pair_rows) {
-        double prod = 1.0;  // exact while below 2^53; only compared with 2^50
-        for (int i = 0; i < pair_rows && i < n; ++i) prod *= (double)s_deg[s_row[i]];
-        pairs_ok = prod < 1125899906842624.0 ? 1 : 0;
+      if (ones0 <= pair_rows && degprod(0, pair_rows) < k2p50) {
+        pairs_ok = 1;
+        if (band >= 1 && n - pair_rows - band >= 1 && s_ones1 <= band &&
+            degprod(pair_rows, pair_rows + band) < k2p50 && degprod(pair_rows + band, n) < k2p50)
+          pairs_ok = 2;
       }
     }
     double lb = 0.0;

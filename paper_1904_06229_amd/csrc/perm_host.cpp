@@ -443,7 +443,9 @@ void fill_common(const Raw& raw, uint64_t count, perm_result* out) {
   out->blocks = raw.blocks;
   out->kernel_ms = raw.kernel_ms;
   out->total_ms = raw.total_ms;
-  out->walk_variant = raw.r.variant;
+  // the banded walk needs chunks of at least 4 terms; with shorter ones the
+  // pair-shared walk ran on the same staged layout
+  out->walk_variant = (raw.r.variant == 2 && raw.plan.log2_chunk < 2) ? 1 : raw.r.variant;
   out->col0_nonzeros = raw.r.variant ? raw.r.ones0 : 0;
   out->parts = raw.parts;
 }

@@ -104,7 +104,9 @@ def test_int01_config_30x30(B, orc, inp):
     want = orc.ryser(A)
     log(f"  per = {want}, kernel {got.kernel_ms:.3f} ms, walk variant {got.walk_variant}")
     assert got.exact == want
-    assert got.walk_variant == 1  # sparsest column has 10 = n/3 ones
+    # sparsest column: 10 = n/3 ones; the next column flipped has 7 ones outside
+    # those 10 rows (at most (n - n/3)/2 = 10): the banded walk
+    assert got.walk_variant == 2
 
 
 def with_sparse_column(rng, n, ones, p=0.5):
@@ -131,9 +133,40 @@ def test_int01_pair_shared_walk(B, orc, inp, n):
         plain = B.perm_int01(dev_cm(A), drift_check=True)  # drift check keeps the plain walk
         assert plain.exact == want and plain.walk_variant == 0
         if engaged:
-            assert got.walk_variant == 1, (n, ones)
+            assert got.walk_variant in (1, 2), (n, ones)
         elif (A.sum(axis=0) > M).all():
             assert got.walk_variant == 0
+
+
+@pytest.mark.parametrize("n", [9, 12, 18, 21, 24, 26])
+def test_int01_banded_walk(B, orc, n):
+    """The banded walk (column 1 flipped after every other pair; the rows with
+    zeros in columns 0 and 1 share one product per two pairs) engages when a
+    column has at most (n - n/3)/2 ones outside the first n/3 rows, and needs
+    chunks of at least 4 terms; every walk is exact."""
+    rng = np.random.default_rng(9000 + n)
+    M = n // 3
+    E = (n - M) // 2
+    # band: column 5 has M ones, column 7 two ones (row sums below n keep every
+    # group's product below 2^50 for n <= 30)
+    A = with_sparse_column(rng, n, M)
+    col = np.zeros(n, dtype=np.uint8)
+    col[rng.choice(n, 2, replace=False)] = 1
+    A[:, 7] = col
+    want = orc.ryser(A)
+    for lc, variant in ((0, 2), (2, 2), (3, 2), (1, 1)):
+        got = B.perm_int01(dev_cm(A), log2_chunk=lc)
+        assert got.exact == want, (n, lc)
+        assert got.walk_variant == variant, (n, lc, got.walk_variant)
+    # no band: every column but the sparse one is all ones, so more than E ones
+    # outside the first M rows
+    A2 = np.ones((n, n), dtype=np.uint8)
+    col = np.zeros(n, dtype=np.uint8)
+    col[rng.choice(n, M, replace=False)] = 1
+    A2[:, 5] = col
+    got = B.perm_int01(dev_cm(A2))
+    assert got.exact == orc.ryser(A2) and got.walk_variant == 1, (n, got.walk_variant)
+    assert n - M > E
 
 
 def test_int01_pair_shared_not_for_dense(B, inp):
