@@ -169,6 +169,23 @@ def test_int01_banded_walk(B, orc, n):
     assert n - M > E
 
 
+def test_int01_banded_walk_block_diagonal_40(B, orc):
+    """n = 40, beyond the oracle's whole 0/1 sums: a 20 (+) 20 block-diagonal
+    Bernoulli(1/2) matrix, whose permanent is the product of its blocks',
+    exactly, through the banded walk (2^39 terms)."""
+    rng = np.random.default_rng(4040)
+    n, h = 40, 20
+    A = np.zeros((n, n), dtype=np.uint8)
+    A[:h, :h] = rng.random((h, h)) < 0.5
+    A[h:, h:] = rng.random((h, h)) < 0.5
+    want = orc.ryser(A[:h, :h]) * orc.ryser(A[h:, h:])
+    got = B.perm_int01(dev_cm(A))
+    log(f"  40x40 block-diagonal 0/1: per = {want}, walk variant {got.walk_variant}, "
+        f"walk {got.kernel_ms:.1f} ms")
+    assert got.exact == want
+    assert got.walk_variant == 2
+
+
 def test_int01_pair_shared_not_for_dense(B, inp):
     r = B.perm_int01(dev(inp.ones(20)))
     assert r.walk_variant == 0 and r.exact == math.factorial(20)
