@@ -244,9 +244,10 @@ __global__ __launch_bounds__(kBlock) void stage_int01_kernel(const uint8_t* __re
     if (tid == 1) {
       src = col1;
     } else if (tid >= 2) {
+      // the (tid - 2)-th column, counting from 0, that is neither of those two
       int k = tid - 2;
-      for (src = 0; src == best || src == col1 || k-- > 0; ++src) {
-      }
+      src = 0;
+      while (src == best || src == col1 || k-- > 0) ++src;
     }
     s_col[tid] = src;
     // rows after group D: a one in column 1 first, then the others, each by
