@@ -80,18 +80,30 @@ typedef const __attribute__((address_space(4))) BatchItem* citem_ptr;
 typedef const __attribute__((address_space(4))) int64_t* ci64_ptr;
 typedef const __attribute__((address_space(4))) int32_t* ci32_ptr;
 
+// Complex sizes whose lanes walk two half-length chunks of the same parity in
+// lockstep (walk_chunks_complex_twin): every scalar column read then serves
+// two walks and each wave has two independent product chains, at two waves
+// per SIMD.  Measured per size against one chunk per lane at four waves:
+// faster at n = 17..20 (by 1.5-11%), slower below (short chunks) and from
+// n = 21 on (the two walks' row sums spill).
+template <int N>
+constexpr bool twin_chunks() {
+  return N >= 17 && N <= 20;
+}
+
 // Smallest waves per SIMD the compiler must keep for size N: up to n = 24
 // the walk fits 4 waves (128 VGPRs) with at most a few spills outside the
 // chunk loop, where it would otherwise take a few registers more and run
-// with 3; larger sizes keep the compiler's choice.
-template <int N>
+// with 3; the twin walk fits 2; larger sizes keep the compiler's choice.
+template <int N, bool CPLX>
 constexpr int batched_min_waves() {
-  return N <= 24 ? 4 : 1;
+  return (CPLX && twin_chunks<N>()) ? 2 : (N <= 24 ? 4 : 1);
 }
 
 // The items [item0, item0 + nitems), all of size N.
 template <int N, int MODE, bool CPLX>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(batched_min_waves<N>())))
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(batched_min_waves<N, CPLX>())))
 void batched_size_kernel(BatchArgs a, uint64_t item0, uint64_t nitems) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint64_t wave = wave_id();
@@ -114,23 +126,45 @@ void batched_size_kernel(BatchArgs a, uint64_t item0, uint64_t nitems) {
     double dr = 0.0;
     dd re{0.0, 0.0}, im{0.0, 0.0};
     // n = 1 has a single term; every larger size is planned with b >= 1.
-    if constexpr (CPLX) {
+    if constexpr (CPLX && twin_chunks<N>()) {
+      if (b >= 2) {
+        // the half-length chunks ca and ca + 2 (same parity); tasks 2k and
+        // 2k + 1 (always both planned) cover the chunks 128k .. 128k + 127
+        // that they cover with whole chunks
+        const uint64_t ca = 4 * (uint64_t(kWave) * (task >> 1) + (uint64_t)lane) + (task & 1);
+        cdd pa, pb;
+        walk_chunks_complex_twin<N, MODE>(st, ca, ca + 2, b - 1, gpar, pa, pb);
+        if (ca < 2 * nchunks) {
+          re = pa.re;
+          im = pa.im;
+        }
+        if (ca + 2 < 2 * nchunks) {
+          re = dd_add(re, pb.re);
+          im = dd_add(im, pb.im);
+        }
+      } else {
+        const cdd p = walk_chunk_complex<N, MODE, false>(st, nullptr, c, b, gpar, dr);
+        if (c < nchunks) {
+          re = p.re;
+          im = p.im;
+        }
+      }
+    } else if constexpr (CPLX) {
       cdd p;
       if constexpr (N == 1)
         p = single_term_complex<N, MODE>(st, c);
       else
         p = walk_chunk_complex<N, MODE, false>(st, nullptr, c, b, gpar, dr);
-      re = p.re;
-      im = p.im;
+      if (c < nchunks) {
+        re = p.re;
+        im = p.im;
+      }
     } else {
       if constexpr (N == 1)
         re = single_term_real<N, MODE>(st, c);
       else
         re = walk_chunk_real<N, MODE, false>(st, nullptr, c, b, gpar, dr);
-    }
-    if (c >= nchunks) {
-      re = dd{0.0, 0.0};
-      im = dd{0.0, 0.0};
+      if (c >= nchunks) re = dd{0.0, 0.0};
     }
     re = wave_sum(re);
     if constexpr (CPLX) im = wave_sum(im);

@@ -194,6 +194,55 @@ __device__ __forceinline__ cdd walk_chunk_complex(const double* __restrict__ sta
   return acc;
 }
 
+// Two aligned chunks Ga and Gb of 2^b terms with the same parity (gpar)
+// walked in lockstep: they flip the same column in the same direction at
+// every step, so every column read serves both.  Returns their sums apart.
+template <int N, int MODE>
+__device__ __forceinline__ void walk_chunks_complex_twin(const double* __restrict__ staged,
+                                                        uint64_t Ga, uint64_t Gb, int b,
+                                                        uint32_t gpar, cdd& acc_a, cdd& acc_b) {
+  staged = opaque(staged);
+  double ar[N], ai[N], br[N], bi[N];
+  form_w_complex<N>(staged, Ga << b, ar, ai);
+  form_w_complex<N>(opaque(staged), Gb << b, br, bi);
+  acc_a = cdd{{0.0, 0.0}, {0.0, 0.0}};
+  acc_b = cdd{{0.0, 0.0}, {0.0, 0.0}};
+  const uint32_t half = 1u << (b - 1);
+  uint32_t t = 0;
+  for (; t + 1 < half; ++t) {
+    double pa0r, pa0i, pa1r, pa1i, pb0r, pb0i, pb1r, pb1i;
+    term_prod_complex<N, MODE>(ar, ai, pa0r, pa0i);
+    term_prod_complex<N, MODE>(br, bi, pb0r, pb0i);
+    add_col_complex<N>(ar, ai, staged, t & 1u, 0);
+    add_col_complex<N>(br, bi, staged, t & 1u, 0);
+    term_prod_complex<N, MODE>(ar, ai, pa1r, pa1i);
+    term_prod_complex<N, MODE>(br, bi, pb1r, pb1i);
+    const uint32_t s1 = 2 * t + 2;
+    const int j = __builtin_ctz(s1);
+    const uint32_t sub = flip_subtracts(s1, j, b, gpar);
+    add_col_complex<N>(ar, ai, staged, sub, j);
+    add_col_complex<N>(br, bi, staged, sub, j);
+    lane_acc<MODE>(acc_a.re, pa1r - pa0r);
+    lane_acc<MODE>(acc_a.im, pa1i - pa0i);
+    lane_acc<MODE>(acc_b.re, pb1r - pb0r);
+    lane_acc<MODE>(acc_b.im, pb1i - pb0i);
+  }
+  {
+    const uint32_t sub0 = (b >= 2) ? (t & 1u) : gpar;
+    double pa0r, pa0i, pa1r, pa1i, pb0r, pb0i, pb1r, pb1i;
+    term_prod_complex<N, MODE>(ar, ai, pa0r, pa0i);
+    term_prod_complex<N, MODE>(br, bi, pb0r, pb0i);
+    add_col_complex<N>(ar, ai, staged, sub0, 0);
+    add_col_complex<N>(br, bi, staged, sub0, 0);
+    term_prod_complex<N, MODE>(ar, ai, pa1r, pa1i);
+    term_prod_complex<N, MODE>(br, bi, pb1r, pb1i);
+    lane_acc<MODE>(acc_a.re, pa1r - pa0r);
+    lane_acc<MODE>(acc_a.im, pa1i - pa0i);
+    lane_acc<MODE>(acc_b.re, pb1r - pb0r);
+    lane_acc<MODE>(acc_b.im, pb1i - pb0i);
+  }
+}
+
 // ------------------------------------------------- rows kept in LDS ----
 // Above n = 48 the complex row sums alone (4n VGPRs) leave room for one wave
 // per SIMD, which cannot hide the latency of the scalar column loads and of

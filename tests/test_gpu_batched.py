@@ -78,15 +78,18 @@ def test_mixed_sizes_vs_oracle(B, orc, inp, is_complex):
 
 
 def test_batched_matches_single(B, inp):
-    """Same matrix (column-major A itself, not A^T), same chunks (2^8 terms):
-    the two paths walk identical chunks and differ only in reduction order."""
+    """Same matrix (column-major A itself, not A^T), same chunks: the two paths
+    walk identical chunks and differ only in reduction order.  Batched chunks
+    of 2^8 terms; at n = 17..20 each lane walks two of their halves, so the
+    single path takes 2^7-term chunks there."""
     mats = [inp.complex_gaussian(n, 900 + n, scale=n ** -0.5) for n in (10, 18, 22, 24, 32)]
     vals, st, _ = run_batched(B, mats, True, log2_chunk=8)
     for M, v in zip(mats, vals):
         col = torch.from_numpy(np.asfortranarray(M)).to("cuda")
         assert col.stride(0) == 1
-        s = B.perm_complex(col, log2_chunk=8).value
-        assert rel(v, s) < 1e-15
+        n = M.shape[0]
+        s = B.perm_complex(col, log2_chunk=7 if 17 <= n <= 20 else 8).value
+        assert rel(v, s) < 1e-15, n
 
 
 def test_haar_blocks_unitary_bound(B, inp):
@@ -111,6 +114,23 @@ def test_chunk_override_and_plain_fp64(B, orc, inp):
         for M, v in zip(mats, vals):
             w = orc.ryser(M)
             assert rel(v, w.hi + w.lo) < TOL
+
+
+@pytest.mark.parametrize("lc", [0, 1, 2, 3, 9, 14])
+def test_twin_chunk_sizes(B, orc, inp, lc):
+    """Complex sizes 17..20 walk two half-length chunks of the same parity per
+    lane in lockstep (tasks 2k and 2k + 1 together cover the chunks they cover
+    one per lane).  Every chunk length against the oracle: 2 terms (b = 1:
+    one chunk per lane), 4 terms (half-chunks of one pair), the default, and
+    2^14 (fewer than 128 chunks per matrix: lanes past the end); n = 16 and 21
+    walk one chunk per lane in the same launches."""
+    mats = [inp.complex_gaussian(n, 300 + n, scale=n ** -0.5) for n in (16, 17, 18, 19, 20, 21)]
+    mats += [inp.complex_gaussian(n, 400 + n, scale=n ** -0.5) for n in (17, 20)]
+    vals, st, _ = run_batched(B, mats, True, log2_chunk=lc)
+    assert (st == 0).all()
+    for M, v in zip(mats, vals):
+        w = orc.ryser(M)
+        assert rel(v, complex(w.re.hi + w.re.lo, w.im.hi + w.im.lo)) < TOL, (M.shape[0], lc)
 
 
 def test_graph_replay_matches_eager(B, inp):
