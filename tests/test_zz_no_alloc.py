@@ -99,3 +99,18 @@ def test_noalloc_options_and_limits(B, inp):
     assert e.value.status == B.PERM_EINVAL
     # the entry point still works after the rejected calls
     assert bits(B.perm_partial_noalloc(dA, 0, 1 << 17)) == bits(B.perm_partial(dA, 0, 1 << 17))
+
+
+def test_noalloc_large_complex_rows_in_lds(B, orc, inp):
+    """Complex n = 64 (the walk keeps rows 46.. of its row sums in LDS, and the
+    fixed array holds the largest +-A copy), then n = 50: the same bits as
+    perm_partial and the oracle's direct terms at the FP64 bar."""
+    for n, seed, start, count in ((64, 33, (1 << 62) + 12345, (1 << 16) + 5), (50, 34, 7, 1 << 14)):
+        A = matrix(inp, "complex", n, seed)
+        dA = dev_cm(A)
+        got = B.perm_partial_noalloc(dA, start, count)
+        ref = B.perm_partial(dA, start, count)
+        assert got.terms == count
+        if got.blocks == ref.blocks:
+            assert bits(got) == bits(ref)
+        assert rel(got, orc.chunk_partial(A, start, count)) < TOL
