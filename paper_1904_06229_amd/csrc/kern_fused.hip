@@ -110,6 +110,7 @@ __device__ __forceinline__ void fused_stage(const FusedArgs& a, double* slot, in
   for (int t = tid; t < TOT; t += kBlock) {
     const int i = (t / CW) % N;
     const double v = ldexp(s_a[t], s_exp[i]);
+    s_a[t] = v;  // the chunk starts read the scaled entries from here
     slot[t] = v;
     slot[TOT + t] = -v;
   }
@@ -119,10 +120,97 @@ __device__ __forceinline__ void fused_stage(const FusedArgs& a, double* slot, in
   __syncthreads();
 }
 
+// Row sums at the start of chunk G (App. A: w = (1/2) sum_j delta_j a_j with
+// delta_{n-1} = +1 and delta_j = 2 x_j - 1, x = gray(G 2^b)), from the scaled
+// entries in LDS (s_a, column-major, CW doubles per entry) and the staged copy
+// in device memory (slot).
+//
+// Every column read by a chunk start on the scalar path costs one scalar-load
+// round trip, and with one wave per SIMD nothing hides it.  Under the lane ->
+// chunk map the 64 lanes of a wave differ only in bits 1..6 of the chunk index,
+// so only the Gray bits of columns b..b+6 differ between them.  The part of w
+// from the other columns is the same for the whole wave: lane k sums component
+// k (row k / CW) over them from LDS, all reads in flight at once, and leaves it
+// in the wave's row of s_u, from where every lane reads the whole vector.  Each
+// lane then adds its own columns b..b+6 on the scalar path.  A wave whose lanes
+// disagree outside b..b+6 forms every column per lane instead.
+template <int N, bool CPLX>
+__device__ __forceinline__ void fused_chunk_start(const double* s_a, double* s_u,
+                                                  const double* slot, uint64_t G, int b,
+                                                  double (&wr)[N], double (&wi)[N]) {
+  constexpr int CW = CPLX ? 2 : 1;
+  const uint64_t x = gray(G << b);
+  const uint64_t xu = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(x >> 32)) << 32) |
+                      __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint64_t lane_cols = 0x7Full << b;
+  const uint64_t cols = (1ull << (N - 1)) - 1;  // columns 0..N-2
+  const uint64_t shared = cols & ~lane_cols;
+  if (__builtin_amdgcn_ballot_w64(((x ^ xu) & shared) != 0) != 0) {
+    if constexpr (CPLX)
+      form_w_complex<N>(slot, G << b, wr, wi);
+    else
+      form_w_real<N>(slot, G << b, wr);
+    return;
+  }
+  const int k = threadIdx.x & (kWave - 1);
+  if (k < CW * N) {
+    const int r = k / CW, c = k - CW * (k / CW);
+    double e[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) e[j] = s_a[CW * (r + j * N) + c];
+    double u = e[N - 1];
+#pragma unroll
+    for (int j = 0; j < N - 1; ++j) {
+      // +1 / -1 by the shared Gray bit; 0 for the lanes' own columns
+      const double d = ((shared >> j) & 1) ? (((xu >> j) & 1) ? 1.0 : -1.0) : 0.0;
+      u = fma(d, e[j], u);
+    }
+    s_u[k] = u;
+  }
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    wr[i] = s_u[CW * i];
+    if constexpr (CPLX) wi[i] = s_u[CW * i + 1];
+  }
+  __builtin_amdgcn_wave_barrier();
+  const int jend = b + 7 < N - 1 ? b + 7 : N - 1;
+#pragma unroll 1
+  for (int j = b; j < jend; ++j) {
+    const double d = ((x >> j) & 1) ? 1.0 : -1.0;
+    cdptr col = as_const(slot + CW * j * N);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      wr[i] = fma(d, col[CW * i], wr[i]);
+      if constexpr (CPLX) wi[i] = fma(d, col[CW * i + 1], wi[i]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    wr[i] *= 0.5;
+    if constexpr (CPLX) wi[i] *= 0.5;
+  }
+}
+
+// Both parts of a complex partial through the same butterfly as wave_sum(dd),
+// side by side (the two chains are independent, so each hides the other's
+// latency); the bits are those of two separate wave_sum calls.
+__device__ __forceinline__ cdd wave_sum_c(cdd v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    const dd o_re{__shfl_xor(v.re.hi, off), __shfl_xor(v.re.lo, off)};
+    const dd o_im{__shfl_xor(v.im.hi, off), __shfl_xor(v.im.lo, off)};
+    v.re = dd_add(v.re, o_re);
+    v.im = dd_add(v.im, o_im);
+  }
+  return v;
+}
+
 template <int N, bool CPLX, int MODE>
 __global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs a) {
   constexpr int CW = CPLX ? 2 : 1;
   __shared__ double s_a[CW * N * N];
+  __shared__ double s_u[kWavesPerBlock][CW * N];
   __shared__ int32_t s_exp[N];
   __shared__ int32_t s_bad;
   __shared__ int32_t s_last;
@@ -136,34 +224,38 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs a) {
   const bool ok = s_bad == 0;
 
   const int lane = tid & (kWave - 1);
+  const int wave_in_block = tid / kWave;
   const uint64_t wave = wave_id();
   const uint64_t nwaves = (uint64_t)gridDim.x * kWavesPerBlock;
   dd re{0.0, 0.0}, im{0.0, 0.0};
-  double dr = 0.0;  // no drift check on this path
   if (ok) {
     for (uint64_t task = wave; task < a.ntasks; task += nwaves) {
       const uint64_t c = task_chunk(task, lane);
       const uint32_t gpar = (uint32_t)(task & 1);
+      const double* staged = opaque(slot);
+      double wr[N], wi[N];
+      fused_chunk_start<N, CPLX>(s_a, s_u[wave_in_block], staged, c, a.b, wr, wi);
       if constexpr (CPLX) {
-        const cdd part = walk_chunk_complex<N, MODE, false>(slot, nullptr, c, a.b, gpar, dr);
+        const cdd part = walk_pairs_complex<N, MODE>(staged, wr, wi, a.b, gpar);
         if (c < a.nchunks) {
           re = dd_add(re, part.re);
           im = dd_add(im, part.im);
         }
       } else {
-        const dd part = walk_chunk_real<N, MODE, false>(slot, nullptr, c, a.b, gpar, dr);
+        const dd part = walk_pairs_real<N, MODE>(staged, wr, a.b, gpar);
         if (c < a.nchunks) re = dd_add(re, part);
       }
     }
   }
-  // this workgroup's partial (as the walk kernels)
-  const dd vr = wave_sum(re);
-  const dd br = block_sum(vr, dd_add);
-  dd bi{0.0, 0.0};
+  // this workgroup's partial (as the walk kernels, in the same order)
+  dd br, bi{0.0, 0.0};
   if constexpr (CPLX) {
-    const dd vi = wave_sum(im);
-    __syncthreads();
-    bi = block_sum(vi, dd_add);
+    const cdd v = wave_sum_c(cdd{re, im});
+    const cdd blk = block_sum(v, [](cdd x, cdd y) { return cdd{dd_add(x.re, y.re), dd_add(x.im, y.im)}; });
+    br = blk.re;
+    bi = blk.im;
+  } else {
+    br = block_sum(wave_sum(re), dd_add);
   }
   if (tid == 0) {
     double* p = a.partials + 4 * (size_t)blockIdx.x;
@@ -171,16 +263,19 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs a) {
     p[1] = br.lo;
     p[2] = bi.hi;
     p[3] = bi.lo;
-    __threadfence();  // the partial is visible device-wide before it is counted
+    // release: the partial is visible device-wide before the count that
+    // announces it (the counter's read-modify-writes form one release sequence)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const uint32_t done = atomicAdd(a.counter, 1u);
     s_last = done == gridDim.x - 1 ? 1 : 0;
   }
   __syncthreads();
   if (!s_last) return;
-  // The last workgroup: every other partial has been counted, so it is visible.
-  // Its first wave adds them -- lane l takes partials l, l + 64, ... in order,
-  // then the lanes meet along the shuffle butterfly -- with no barrier.
-  __threadfence();
+  // The last workgroup: every other partial has been counted; the acquire makes
+  // them visible.  Its first wave adds them -- lane l takes partials l, l + 64,
+  // ... in order, then the lanes meet along the shuffle butterfly -- with no
+  // barrier.
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   if (tid >= kWave) return;
   const int nparts = (int)gridDim.x;
   re = dd{0.0, 0.0};

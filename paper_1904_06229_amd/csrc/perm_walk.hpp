@@ -54,14 +54,11 @@ __device__ __forceinline__ dd single_term_real(const double* __restrict__ staged
   return dd{(g & 1) ? p : -p, 0.0};
 }
 
-// Signed sum of the terms of chunk G (Gray indices [G*L, (G+1)*L)), b >= 1.
-template <int N, int MODE, bool DRIFT>
-__device__ __forceinline__ dd walk_chunk_real(const double* __restrict__ staged,
-                                         const double* __restrict__ rowabs, uint64_t G, int b,
-                                         uint32_t gpar, double& drift) {
-  staged = opaque(staged);
-  double w[N];
-  form_w_real<N>(staged, G << b, w);
+// Signed sum of the 2^b terms of an aligned chunk whose start row sums are w
+// (b >= 1); w ends as the row sums of the chunk's last term.
+template <int N, int MODE>
+__device__ __forceinline__ dd walk_pairs_real(const double* __restrict__ staged, double (&w)[N],
+                                              int b, uint32_t gpar) {
   dd acc{0.0, 0.0};
   const uint32_t half = 1u << (b - 1);
   uint32_t t = 0;
@@ -82,6 +79,18 @@ __device__ __forceinline__ dd walk_chunk_real(const double* __restrict__ staged,
     const double p1 = term_prod_real<N, MODE>(w);
     lane_acc<MODE>(acc, p1 - p0);
   }
+  return acc;
+}
+
+// Signed sum of the terms of chunk G (Gray indices [G*L, (G+1)*L)), b >= 1.
+template <int N, int MODE, bool DRIFT>
+__device__ __forceinline__ dd walk_chunk_real(const double* __restrict__ staged,
+                                         const double* __restrict__ rowabs, uint64_t G, int b,
+                                         uint32_t gpar, double& drift) {
+  staged = opaque(staged);
+  double w[N];
+  form_w_real<N>(staged, G << b, w);
+  const dd acc = walk_pairs_real<N, MODE>(staged, w, b, gpar);
   if constexpr (DRIFT) {
     double f[N];
     form_w_real<N>(staged, ((G + 1) << b) - 1, f);
@@ -152,14 +161,12 @@ __device__ __forceinline__ cdd single_term_complex(const double* __restrict__ st
   return cdd{{pos ? pr : -pr, 0.0}, {pos ? pi : -pi, 0.0}};
 }
 
-// Signed sums of chunk G's terms, b >= 1.
-template <int N, int MODE, bool DRIFT>
-__device__ __forceinline__ cdd walk_chunk_complex(const double* __restrict__ staged,
-                                          const double* __restrict__ rowabs, uint64_t G, int b,
-                                          uint32_t gpar, double& drift) {
-  staged = opaque(staged);
-  double wr[N], wi[N];
-  form_w_complex<N>(staged, G << b, wr, wi);
+// Signed sums of the 2^b terms of an aligned chunk whose start row sums are
+// (wr, wi) (b >= 1); they end as the row sums of the chunk's last term.
+template <int N, int MODE>
+__device__ __forceinline__ cdd walk_pairs_complex(const double* __restrict__ staged,
+                                                  double (&wr)[N], double (&wi)[N], int b,
+                                                  uint32_t gpar) {
   cdd acc{{0.0, 0.0}, {0.0, 0.0}};
   const uint32_t half = 1u << (b - 1);
   uint32_t t = 0;
@@ -182,6 +189,18 @@ __device__ __forceinline__ cdd walk_chunk_complex(const double* __restrict__ sta
     lane_acc<MODE>(acc.re, p1r - p0r);
     lane_acc<MODE>(acc.im, p1i - p0i);
   }
+  return acc;
+}
+
+// Signed sums of chunk G's terms, b >= 1.
+template <int N, int MODE, bool DRIFT>
+__device__ __forceinline__ cdd walk_chunk_complex(const double* __restrict__ staged,
+                                          const double* __restrict__ rowabs, uint64_t G, int b,
+                                          uint32_t gpar, double& drift) {
+  staged = opaque(staged);
+  double wr[N], wi[N];
+  form_w_complex<N>(staged, G << b, wr, wi);
+  const cdd acc = walk_pairs_complex<N, MODE>(staged, wr, wi, b, gpar);
   if constexpr (DRIFT) {
     double fr[N], fi[N];
     form_w_complex<N>(staged, ((G + 1) << b) - 1, fr, fi);

@@ -81,14 +81,17 @@ def test_batched_matches_single(B, inp):
     """Same matrix (column-major A itself, not A^T), same chunks: the two paths
     walk identical chunks and differ only in reduction order.  Batched chunks
     of 2^8 terms; at n = 17..20 each lane walks two of their halves, so the
-    single path takes 2^7-term chunks there."""
+    single path takes 2^7-term chunks there.  The single calls take an explicit
+    grid, hence the three-launch path, whose chunk starts are formed column by
+    column in the batched walk's order (the one-launch path sums the columns
+    shared by a wave first, a different rounding)."""
     mats = [inp.complex_gaussian(n, 900 + n, scale=n ** -0.5) for n in (10, 18, 22, 24, 32)]
     vals, st, _ = run_batched(B, mats, True, log2_chunk=8)
     for M, v in zip(mats, vals):
         col = torch.from_numpy(np.asfortranarray(M)).to("cuda")
         assert col.stride(0) == 1
         n = M.shape[0]
-        s = B.perm_complex(col, log2_chunk=7 if 17 <= n <= 20 else 8).value
+        s = B.perm_complex(col, log2_chunk=7 if 17 <= n <= 20 else 8, blocks=256).value
         assert rel(v, s) < 1e-15, n
 
 
