@@ -95,6 +95,25 @@ def test_one_launch_precisions_and_scaling(B, orc, inp):
     assert rel(c, d) < 1e-13
 
 
+@pytest.mark.parametrize("kind,n", [("complex", 20), ("real", 13), ("complex", 9)])
+def test_one_launch_chunk_lengths(B, orc, inp, kind, n):
+    """Every chunk length takes the one launch, and with it the chunk starts
+    whose part shared by a wave's lanes (all columns but b..b+6) comes from
+    LDS: b = 1 puts the lanes' own columns at the bottom, larger b moves them
+    up until none of the shared columns lie above them."""
+    if kind == "real":
+        A, fn = inp.real_gaussian(n, 1300 + n), B.perm_real
+    else:
+        A, fn = inp.complex_gaussian(n, 1400 + n, scale=n ** -0.5), B.perm_complex
+    want = orc.ryser(A)
+    three = fn(dev(A), blocks=64)
+    for lc in range(1, min(8, n - 1) + 1):
+        r = fn(dev(A), log2_chunk=lc)
+        assert r.log2_chunk == lc and r.walk_variant == 1, (lc, r.walk_variant)
+        assert rel(r, want) < TOL, lc
+        assert rel(r, three) < 1e-13, lc
+
+
 def test_one_launch_counter_survives_errors(B, inp):
     A = inp.complex_gaussian(16, 5, scale=0.25)
     before = B.perm_complex(dev(A))
