@@ -12,8 +12,10 @@
 //      walk reads its columns with scalar loads.  The slot is written and
 //      read by this workgroup only; the stores are waited for before the
 //      barrier, so the scalar loads (which go to L2) find them;
-//   2. the waves walk their chunks exactly as walk_real_kernel /
-//      walk_complex_kernel do (same lane -> chunk map, same pair loop);
+//   2. the waves walk their chunks as walk_real_kernel / walk_complex_kernel
+//      do (same lane -> chunk map, same pair loop); only the chunk starts are
+//      formed differently, the columns shared by a wave's lanes from LDS (see
+//      fused_chunk_start), so the last bits can differ from those paths;
 //   3. each workgroup writes its double-double partial, and the workgroup
 //      that finishes last (a device-wide completion counter) adds all
 //      partials in a fixed order (one wave: strided lane sums, then the
