@@ -81,12 +81,16 @@ __device__ __forceinline__ void fused_stage(const FusedArgs& a, double* slot, in
       mx = fmax(mx, __shfl_xor(mx, off));
       bad |= __shfl_xor(bad, off);
     }
+    // the row scaled by 2^-k1 (mx = f 2^k1, f in [1/2, 1)): exact, no division,
+    // every entry at most 1 in magnitude
+    int k1 = 0;
+    (void)frexp(mx, &k1);
     double ss = 0.0;
     if (i < N && !bad && mx > 0.0) {
       for (int j = sub; j < N; j += kRowThreads)
 #pragma unroll
         for (int c = 0; c < CW; ++c) {
-          const double x = s_a[CW * (i + j * N) + c] / mx;
+          const double x = ldexp(s_a[CW * (i + j * N) + c], -k1);
           ss += x * x;
         }
     }
@@ -95,12 +99,11 @@ __device__ __forceinline__ void fused_stage(const FusedArgs& a, double* slot, in
     if (i < N && sub == 0) {
       int e = 0;
       if (!bad && a.row_scaling && mx > 0.0) {
-        // norm = mx sqrt(ss) in [2^(k-1), 2^k): exponents taken apart so a row
-        // near the top of the double range does not overflow the product
-        int k1, k2;
-        const double f = frexp(mx, &k1) * frexp(sqrt(ss), &k2);  // in [1/4, 1)
-        int k = k1 + k2;
-        if (f < 0.5) --k;
+        // norm = 2^k1 sqrt(ss) in [2^(k-1), 2^k) with k = k1 + k2, sqrt(ss) =
+        // g 2^k2, g in [1/2, 1)
+        int k2;
+        (void)frexp(sqrt(ss), &k2);
+        const int k = k1 + k2;
         e = 2 - k;
         e = e < -1000 ? -1000 : (e > 1000 ? 1000 : e);
       }
