@@ -38,6 +38,23 @@ namespace {
 constexpr int kRowThreads = 8;
 static_assert(kFusedMaxN * kRowThreads <= kBlock, "row statistics need a thread group per row");
 
+// Lane moves inside groups of kRowThreads = 8 lanes (DPP, no LDS round trip):
+// swap neighbours, swap pairs, then mirror the group (lane i <-> 7 - i).  The
+// three steps give every lane of the group the combination of all eight.
+constexpr int kDppXor1 = 0xB1;    // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;    // quad_perm [2, 3, 0, 1]
+constexpr int kDppMirror8 = 0x141;  // row_half_mirror
+static_assert(kRowThreads == 8, "the DPP steps combine groups of 8 lanes");
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 template <int N, bool CPLX>
 __device__ __forceinline__ void fused_stage(const FusedArgs& a, double* slot, int32_t* s_exp,
                                             int32_t* s_bad, double* s_a) {
@@ -62,7 +79,7 @@ __device__ __forceinline__ void fused_stage(const FusedArgs& a, double* slot, in
   }
   __syncthreads();
   // row statistics: kRowThreads threads per row, each over every
-  // kRowThreads-th column, combined by shuffles inside the group (fixed order)
+  // kRowThreads-th column, combined by DPP lane moves inside the group (fixed order)
   {
     const int i = tid / kRowThreads, sub = tid % kRowThreads;
     double mx = 0.0;
@@ -76,11 +93,12 @@ __device__ __forceinline__ void fused_stage(const FusedArgs& a, double* slot, in
           mx = fmax(mx, fabs(x));
         }
     }
-#pragma unroll
-    for (int off = 1; off < kRowThreads; off <<= 1) {
-      mx = fmax(mx, __shfl_xor(mx, off));
-      bad |= __shfl_xor(bad, off);
-    }
+    mx = fmax(mx, dpp_f64<kDppXor1>(mx));
+    bad |= __builtin_amdgcn_mov_dpp(bad, kDppXor1, 0xF, 0xF, false);
+    mx = fmax(mx, dpp_f64<kDppXor2>(mx));
+    bad |= __builtin_amdgcn_mov_dpp(bad, kDppXor2, 0xF, 0xF, false);
+    mx = fmax(mx, dpp_f64<kDppMirror8>(mx));
+    bad |= __builtin_amdgcn_mov_dpp(bad, kDppMirror8, 0xF, 0xF, false);
     // the row scaled by 2^-k1 (mx = f 2^k1, f in [1/2, 1)): exact, no division,
     // every entry at most 1 in magnitude
     int k1 = 0;
@@ -94,8 +112,9 @@ __device__ __forceinline__ void fused_stage(const FusedArgs& a, double* slot, in
           ss += x * x;
         }
     }
-#pragma unroll
-    for (int off = 1; off < kRowThreads; off <<= 1) ss += __shfl_xor(ss, off);
+    ss += dpp_f64<kDppXor1>(ss);
+    ss += dpp_f64<kDppXor2>(ss);
+    ss += dpp_f64<kDppMirror8>(ss);
     if (i < N && sub == 0) {
       int e = 0;
       if (!bad && a.row_scaling && mx > 0.0) {
