@@ -216,12 +216,28 @@ __device__ __forceinline__ void fused_chunk_start(const double* s_a, double* s_u
   }
 }
 
-// Both parts of a complex partial through the same butterfly as wave_sum(dd),
-// side by side (the two chains are independent, so each hides the other's
-// latency); the bits are those of two separate wave_sum calls.
+constexpr int kDppMirror16 = 0x140;  // row_mirror: lane i <-> 15 - i in each row of 16
+
+template <int CTRL>
+__device__ __forceinline__ void wave_step_dpp(cdd& v) {
+  const dd o_re{dpp_f64<CTRL>(v.re.hi), dpp_f64<CTRL>(v.re.lo)};
+  const dd o_im{dpp_f64<CTRL>(v.im.hi), dpp_f64<CTRL>(v.im.lo)};
+  v.re = dd_add(v.re, o_re);
+  v.im = dd_add(v.im, o_im);
+}
+
+// Both parts of a complex partial summed over the wave, side by side (the two
+// chains are independent, so each hides the other's latency), in a fixed
+// order: within groups of 2, 4, 8 and 16 lanes by DPP lane moves (no LDS round
+// trip), then across the rows of 16 by shuffles.  Every lane ends with the
+// wave's sum.
 __device__ __forceinline__ cdd wave_sum_c(cdd v) {
+  wave_step_dpp<kDppXor1>(v);
+  wave_step_dpp<kDppXor2>(v);
+  wave_step_dpp<kDppMirror8>(v);
+  wave_step_dpp<kDppMirror16>(v);
 #pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) {
+  for (int off = 16; off < kWave; off <<= 1) {
     const dd o_re{__shfl_xor(v.re.hi, off), __shfl_xor(v.re.lo, off)};
     const dd o_im{__shfl_xor(v.im.hi, off), __shfl_xor(v.im.lo, off)};
     v.re = dd_add(v.re, o_re);
@@ -271,7 +287,8 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs a) {
       }
     }
   }
-  // this workgroup's partial (as the walk kernels, in the same order)
+  // this workgroup's partial (the walk kernels' reduction; the complex wave sum has
+  // its own fixed order)
   dd br, bi{0.0, 0.0};
   if constexpr (CPLX) {
     const cdd v = wave_sum_c(cdd{re, im});
